@@ -1,0 +1,226 @@
+/*
+ * mfmg — matrix-free multigrid on locally refined hexahedral meshes, MI355X.
+ *
+ * C ABI of the hot path of the solver described in
+ *   M. Munch, T. Heister, L. Prieto Saavedra, M. Kronbichler,
+ *   "Efficient distributed matrix-free multigrid methods on locally refined
+ *    meshes for FEM computations", arXiv 2203.12292.
+ *
+ * Problem: -Laplace(u) = f on a cube, u = 0 on its boundary, continuous Q_k
+ * Lagrange elements (Gauss-Lobatto nodes, Gauss quadrature with (k+1)^3
+ * points) on an octree mesh whose touching leaves differ by at most one level.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: MFMG_OK (0) or a negative MFMG_ERR_* code; the message of
+ *    the last error of the calling thread is returned by mfmg_last_error().
+ *    Invalid handles, levels, dtypes, degrees or null pointers give
+ *    MFMG_ERR_INVALID_ARG / MFMG_ERR_UNSUPPORTED and change nothing.
+ *  - Vectors hold the *free* DoFs of a level only (Dirichlet and hanging-node
+ *    DoFs are constraints, Section 3.1, not unknowns).  With n_vec > 1 the
+ *    layout is DoF-major interleaved: entry (i, v) at index i*n_vec + v.
+ *  - Vector arguments are device pointers (hipMalloc'd or torch CUDA/HIP
+ *    tensors), contiguous, owned by the caller, of the element type named by
+ *    the dtype argument (double, float, or bfloat16 as uint16 bits).
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls marked
+ *    [async] only enqueue work on it; the others synchronise it.
+ *  - The library owns mesh and level data; it allocates device memory in
+ *    mfmg_setup_levels (metadata, per-level work vectors) and frees it in
+ *    mfmg_destroy_ctx.  The calls below allocate nothing else, except
+ *    mfmg_solve / mfmg_vcycle for n_vec > max_rhs (rejected) and the learned
+ *    correction set-up.
+ */
+#ifndef MFMG_H
+#define MFMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfmg_mesh_s* mfmg_mesh;
+typedef struct mfmg_ctx_s* mfmg_ctx;
+
+enum {
+  MFMG_OK = 0,
+  MFMG_ERR_INVALID_ARG = -1,
+  MFMG_ERR_UNSUPPORTED = -2,
+  MFMG_ERR_HIP = -3,
+  MFMG_ERR_OOM = -4,
+  MFMG_ERR_NOT_CONVERGED = -5,
+  MFMG_ERR_BREAKDOWN = -6,
+  MFMG_ERR_NET_REJECTED = -7 /* informational: learned correction rejected, fallback used */
+};
+
+typedef enum { MFMG_F64 = 0, MFMG_F32 = 1, MFMG_BF16 = 2 } mfmg_dtype;
+
+/* Refinement criteria of the test meshes (Section 4, "Examples"); c = cell
+ * centre.  ALL: every cell.  BALL (x0,y0,z0,r): |c-x0|^2 <= r^2.
+ * BOX_LE (a,b,c): c <= (a,b,c) componentwise (the paper's octant).
+ * BAND (x0,y0,z0,r1,r2): r1^2 <= |c-x0|^2 <= r2^2 (the paper's shell).
+ * SPHERE_CUT (x0,y0,z0,ra,rb): the closed cell box meets the sphere of radius
+ * ra (or rb, if rb > 0) about x0. */
+enum { MFMG_PRED_ALL = 0, MFMG_PRED_BALL = 1, MFMG_PRED_BOX_LE = 2, MFMG_PRED_BAND = 3,
+       MFMG_PRED_SPHERE_CUT = 4 };
+
+#define MFMG_MAX_STEPS 16
+#define MFMG_MAX_LEVELS 32
+
+typedef struct {
+  int n0;          /* coarse grid n0^3 cubes */
+  double lo, hi;   /* domain [lo, hi]^3 */
+  int n_global;    /* uniform refinements first */
+  int n_steps;     /* then one refinement per step, each followed by closure */
+  int kind[MFMG_MAX_STEPS];
+  double params[MFMG_MAX_STEPS][8];
+} mfmg_mesh_desc;
+
+/* Level sequences (coarse to fine):
+ *  H        geometric global coarsening at the fine degree (Section 2.2);
+ *  P_THEN_H polynomial coarsening p_c = floor(p_f/2) on the fine mesh
+ *           (Section 2.3), then geometric global coarsening at degree 1;
+ *  H_THEN_P geometric global coarsening at the fine degree, then polynomial
+ *           coarsening on the coarse grid (keeps the coarse problem small). */
+enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2 };
+
+typedef struct {
+  int degree;            /* finest degree k, 1 <= k <= 6 */
+  int scheme;            /* MFMG_SCHEME_* */
+  int dirichlet;         /* 1: homogeneous Dirichlet on the whole boundary */
+  int n_level_dtype;     /* entries used in level_dtype (0: all MFMG_F64) */
+  int level_dtype[MFMG_MAX_LEVELS]; /* storage type of V-cycle level vectors,
+                                       index 0 = coarsest; missing = last entry */
+  int cheb_degree;       /* Chebyshev degree (paper: 3), 0 -> 3 */
+  double smoothing_range;/* lambda_min = lambda_max / range, 0 -> 20 */
+  double eig_safety;     /* lambda_max = safety * estimate, 0 -> 1.2 */
+  int eig_iterations;    /* CG-Lanczos steps for the estimate, 0 -> 15 */
+  int max_rhs;           /* largest n_vec of vcycle/solve, 0 -> 1 (max 8) */
+} mfmg_level_desc;
+
+typedef struct {
+  int iterations;
+  int converged;
+  double initial_residual;   /* ||b||_2 */
+  double final_residual;     /* ||b - A x||_2 / ||b||_2 (worst over vectors) */
+  double residual_history[256];
+  double time_ms;            /* solve time, set-up excluded */
+  int coarse_fallbacks;      /* learned correction rejected -> exact solve */
+  int coarse_accepted;       /* learned correction accepted */
+} mfmg_solve_stats;
+
+/* ---- set-up (host; synchronous) ----------------------------------------- */
+
+/* Builds the mesh (refinement + one-irregularity closure, Section 4) and its
+ * global-coarsening sequence (Section 2.2): all terminal families are
+ * coarsened at once and the closure re-applied until the coarse grid is left.
+ * *out is owned by the caller until mfmg_destroy_mesh. */
+int mfmg_setup_mesh(const mfmg_mesh_desc* desc, mfmg_mesh* out);
+
+/* Number of global-coarsening meshes (>= 1) and the leaf count of each,
+ * index 0 = coarse grid; cells may be NULL.  n_hanging_cells (optional) gets
+ * the number of leaves of the finest mesh with hanging-node constraints. */
+int mfmg_mesh_info(mfmg_mesh mesh, int* n_meshes, int64_t* cells, int64_t* n_hanging_cells);
+
+/* Builds the multigrid levels on the GPU: DoF numbering, per-cell gather maps
+ * with hanging-node masks (Section 3.2, constraints applied in the gather),
+ * transfer categories and valence weights (Section 3.5), the diagonal
+ * (Eq. impl:mf:diagonal), Chebyshev intervals and the exact coarse solver.
+ * The mesh handle may be destroyed afterwards. */
+int mfmg_setup_levels(mfmg_mesh mesh, const mfmg_level_desc* desc, void* stream, mfmg_ctx* out);
+
+int mfmg_n_levels(mfmg_ctx ctx, int* n_levels);
+
+/* level: 0 = coarsest.  Any output pointer may be NULL. */
+int mfmg_level_info(mfmg_ctx ctx, int level, int64_t* n_dofs, int64_t* n_cells, int* degree,
+                    int* dtype, int64_t* n_hanging_cells);
+
+/* Exact position code of every free DoF (host array [n_dofs][3]).  Per axis:
+ * a lattice point of the level-20 lattice P (cell vertices, and the middle
+ * Gauss-Lobatto node of an interval for even k) is coded 2P; the a-th node of
+ * interval i of level l otherwise is 2*(((l<<25)+i)*16+a)+1.  Equal codes mean
+ * the same point; used to match DoFs with an independent implementation. */
+int mfmg_level_dof_codes(mfmg_ctx ctx, int level, int64_t* codes);
+
+/* Smoother interval [lambda_min, lambda_max] of D^{-1}A used by level l. */
+int mfmg_smoother_range(mfmg_ctx ctx, int level, double* lambda_min, double* lambda_max);
+
+/* Host-only inspection (no GPU needed): DoF numbering of global-coarsening
+ * mesh `mesh_index` (0 = coarse grid) at degree k, and the assembled matrix
+ * sum_e C_e^T A_e C_e built from the same per-cell gather maps and hanging-node
+ * line rules the kernels use.  Call with codes = dense = NULL to get *n_dofs;
+ * then codes ([n_dofs][3], as mfmg_level_dof_codes) and/or dense
+ * ([n_dofs][n_dofs] row-major, only for n_dofs <= 20000) are filled. */
+int mfmg_host_level_matrix(mfmg_mesh mesh, int mesh_index, int degree, int dirichlet, int64_t* n_dofs,
+                           int64_t* codes, double* dense);
+
+/* ---- hot path (device; [async] on `stream`) ----------------------------- */
+
+/* [async] dst = A^(l) src, Eq. (impl:mf): per cell gather G_e with the
+ * hanging-node constraints C_e applied in registers/LDS by 1D interpolation,
+ * sum-factorised evaluation S_e, quadrature-point scaling Q_e, transposed
+ * steps, constrained scatter-add.  dst and src must not alias. */
+int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src,
+               void* stream);
+
+/* [async] diag = diagonal of A^(l) (Eq. impl:mf:diagonal, unit-vector
+ * applications per cell with C_e applied from both sides). */
+int mfmg_diagonal(mfmg_ctx ctx, int level, int dtype, void* diag, void* stream);
+
+/* [async] Chebyshev smoothing of degree cheb_degree around point Jacobi
+ * (Section 3.3) of A^(l) x = b; x_is_zero: start from x = 0 (skips one
+ * operator evaluation).  lambda: NULL for the set-up interval, else
+ * {lambda_min, lambda_max}.  Uses the level's internal work vectors. */
+int mfmg_smooth(mfmg_ctx ctx, int level, int dtype, int n_vec, void* x, const void* b,
+                int x_is_zero, const double* lambda, void* stream);
+
+/* [async] r = b - A^(l) x (Algorithm 2, residual step). */
+int mfmg_residual(mfmg_ctx ctx, int level, int dtype, int n_vec, void* r, const void* b,
+                  const void* x, void* stream);
+
+/* [async] dst_fine += P src_coarse between level fine_level-1 and fine_level
+ * (Eq. eq:impl:loop:categorized: coarse gather with constraints, category
+ * prolongation, valence weights W, scatter). */
+int mfmg_prolongate_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* dst_fine,
+                        const void* src_coarse, void* stream);
+
+/* [async] dst_coarse += P^T src_fine (restriction = transposed prolongation). */
+int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* dst_coarse,
+                      const void* src_fine, void* stream);
+
+/* [async] x = A^(0)^{-1} b on the coarsest level (exact: dense inverse from a
+ * host Cholesky factorisation of the assembled coarse matrix). */
+int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b, void* stream);
+
+/* [async] Algorithm 1: copy b (FP64) to the finest level in that level's
+ * storage type, one V-cycle (Algorithm 2, global-coarsening branch), copy x
+ * back to FP64.  n_vec <= max_rhs. */
+int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* stream);
+
+/* FP64 conjugate gradients preconditioned by one V-cycle per iteration
+ * (Section 2), x0 = 0, stopped when ||b - A x||_2 <= rtol ||b||_2 for every
+ * vector (n_vec vectors in lock step).  flexible = 1 uses the Polak-Ribiere
+ * beta (needed when the preconditioner is not a fixed linear operator).
+ * Returns MFMG_ERR_NOT_CONVERGED after max_it iterations (x holds the last
+ * iterate), MFMG_ERR_BREAKDOWN if p^T A p <= 0.  Synchronous. */
+int mfmg_solve(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, double rtol, int max_it,
+               int flexible, mfmg_solve_stats* stats, void* stream);
+
+/* Load vector b_i = int f phi_i (Gauss (k+1)^3 points, constraints
+ * applied, Dirichlet rows 0) on level l in FP64.  kind 0: f = params[0];
+ * kind 1: f = sum of n_terms Gaussians a exp(-|x-c|^2/(2w^2)), rows
+ * (cx,cy,cz,w,a) in params (host memory), n_terms rows per vector.
+ * Synchronises `stream` (params are staged through device memory). */
+enum { MFMG_RHS_CONST = 0, MFMG_RHS_GAUSS = 1 };
+int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_terms, int n_vec,
+             void* b_f64, void* stream);
+
+/* ---- teardown ------------------------------------------------------------ */
+void mfmg_destroy_ctx(mfmg_ctx ctx);
+void mfmg_destroy_mesh(mfmg_mesh mesh);
+const char* mfmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFMG_H */

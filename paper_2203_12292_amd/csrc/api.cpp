@@ -1,0 +1,336 @@
+// extern "C" entry points (include/mfmg.h).
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "context.hpp"
+#include "fe1d.hpp"
+
+struct mfmg_ctx_s {
+  mfmg::Context ctx;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const mfmg::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(MFMG_ERR_INVALID_ARG, e.what());
+  }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void check_dtype(int dt) {
+  MFMG_REQUIRE(dt == MFMG_F64 || dt == MFMG_F32 || dt == MFMG_BF16, MFMG_ERR_UNSUPPORTED, "unknown dtype");
+}
+
+void check_ptr(const void* p, const char* name) {
+  MFMG_REQUIRE(p != nullptr, MFMG_ERR_INVALID_ARG, std::string("null pointer: ") + name);
+}
+
+void check_nv(mfmg::Context& c, int nv) {
+  MFMG_REQUIRE(nv >= 1 && nv <= 8, MFMG_ERR_INVALID_ARG, "n_vec must be in [1, 8]");
+  (void)c;
+}
+}  // namespace
+
+extern "C" {
+
+const char* mfmg_last_error(void) { return g_last_error.c_str(); }
+
+int mfmg_setup_mesh(const mfmg_mesh_desc* desc, mfmg_mesh* out) {
+  return guarded([&] {
+    check_ptr(desc, "desc");
+    check_ptr(out, "out");
+    *out = nullptr;
+    auto* m = new mfmg_mesh_s();
+    try {
+      m->gc.push_back(mfmg::build_octree(*desc));
+      while (!m->gc.back().is_coarse_grid()) m->gc.push_back(m->gc.back().coarsened());
+      std::reverse(m->gc.begin(), m->gc.end());  // index 0 = coarse grid
+      int64_t nh = 0;
+      for (const mfmg::Cell& c : m->gc.back().leaves()) nh += mfmg::leaf_has_hanging(m->gc.back(), c) ? 1 : 0;
+      m->n_hanging_fine = nh;
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_mesh_info(mfmg_mesh mesh, int* n_meshes, int64_t* cells, int64_t* n_hanging_cells) {
+  return guarded([&] {
+    check_ptr(mesh, "mesh");
+    if (n_meshes) *n_meshes = static_cast<int>(mesh->gc.size());
+    if (cells)
+      for (size_t i = 0; i < mesh->gc.size(); ++i) cells[i] = mesh->gc[i].n_leaves();
+    if (n_hanging_cells) *n_hanging_cells = mesh->n_hanging_fine;
+    return MFMG_OK;
+  });
+}
+
+void mfmg_destroy_mesh(mfmg_mesh mesh) { delete mesh; }
+
+int mfmg_host_level_matrix(mfmg_mesh mesh, int mesh_index, int degree, int dirichlet, int64_t* n_dofs,
+                           int64_t* codes, double* dense) {
+  return guarded([&] {
+    check_ptr(mesh, "mesh");
+    check_ptr(n_dofs, "n_dofs");
+    MFMG_REQUIRE(mesh_index >= 0 && mesh_index < static_cast<int>(mesh->gc.size()), MFMG_ERR_INVALID_ARG,
+                 "mesh index");
+    mfmg::LevelDofs H = mfmg::build_level_dofs(mesh->gc[mesh_index], degree, dirichlet != 0);
+    *n_dofs = H.n_dofs;
+    if (codes) std::memcpy(codes, H.codes.data(), H.codes.size() * sizeof(int64_t));
+    if (dense) {
+      MFMG_REQUIRE(H.n_dofs <= 20000, MFMG_ERR_UNSUPPORTED, "dense matrix too large");
+      std::vector<double> A = mfmg::assemble_dense(H, mfmg::Tables1D(degree));
+      std::memcpy(dense, A.data(), A.size() * sizeof(double));
+    }
+    return MFMG_OK;
+  });
+}
+
+int mfmg_setup_levels(mfmg_mesh mesh, const mfmg_level_desc* desc, void* stream, mfmg_ctx* out) {
+  return guarded([&] {
+    check_ptr(mesh, "mesh");
+    check_ptr(desc, "desc");
+    check_ptr(out, "out");
+    *out = nullptr;
+    auto* c = new mfmg_ctx_s();
+    try {
+      mfmg::setup_context(c->ctx, *mesh, *desc, as_stream(stream));
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+    return MFMG_OK;
+  });
+}
+
+void mfmg_destroy_ctx(mfmg_ctx ctx) {
+  if (ctx) {
+    (void)hipDeviceSynchronize();
+    delete ctx;
+  }
+}
+
+int mfmg_n_levels(mfmg_ctx ctx, int* n_levels) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(n_levels, "n_levels");
+    *n_levels = static_cast<int>(ctx->ctx.levels.size());
+    return MFMG_OK;
+  });
+}
+
+int mfmg_level_info(mfmg_ctx ctx, int level, int64_t* n_dofs, int64_t* n_cells, int* degree, int* dtype,
+                    int64_t* n_hanging_cells) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (n_dofs) *n_dofs = L.n_dofs;
+    if (n_cells) *n_cells = L.n_cells;
+    if (degree) *degree = L.k;
+    if (dtype) *dtype = L.dtype;
+    if (n_hanging_cells) *n_hanging_cells = L.n_hanging;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_level_dof_codes(mfmg_ctx ctx, int level, int64_t* codes) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(codes, "codes");
+    mfmg::Level& L = ctx->ctx.level(level);
+    mfmg::LevelDofs H = mfmg::build_level_dofs(ctx->ctx.meshes[L.mesh], L.k, ctx->ctx.desc.dirichlet != 0);
+    MFMG_REQUIRE(H.n_dofs == L.n_dofs, MFMG_ERR_INVALID_ARG, "inconsistent level");
+    std::memcpy(codes, H.codes.data(), H.codes.size() * sizeof(int64_t));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_smoother_range(mfmg_ctx ctx, int level, double* lambda_min, double* lambda_max) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (lambda_min) *lambda_min = L.lmin;
+    if (lambda_max) *lambda_max = L.lmax;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(dst, "dst");
+    check_ptr(src, "src");
+    check_dtype(dtype);
+    check_nv(ctx->ctx, n_vec);
+    MFMG_REQUIRE(dst != src, MFMG_ERR_INVALID_ARG, "dst and src must not alias");
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (dtype == MFMG_BF16) {
+      MFMG_REQUIRE(n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs for bfloat16");
+      mfmg::launch_vmult(L.view, dtype, n_vec, L.t.ptr, src, as_stream(stream));
+      mfmg::launch_acc_to_storage(dtype, L.n_dofs * n_vec, L.t.ptr, dst, as_stream(stream));
+    } else {
+      mfmg::launch_vmult(L.view, dtype, n_vec, dst, src, as_stream(stream));
+    }
+    return MFMG_OK;
+  });
+}
+
+int mfmg_diagonal(mfmg_ctx ctx, int level, int dtype, void* diag, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(diag, "diag");
+    check_dtype(dtype);
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (dtype == MFMG_F64) {
+      mfmg::launch_diagonal(L.view, static_cast<double*>(diag), as_stream(stream));
+    } else {
+      mfmg::launch_diagonal(L.view, reinterpret_cast<double*>(L.t.ptr), as_stream(stream));
+      mfmg::launch_cast(MFMG_F64, dtype, L.n_dofs, L.t.ptr, diag, as_stream(stream));
+    }
+    return MFMG_OK;
+  });
+}
+
+int mfmg_smooth(mfmg_ctx ctx, int level, int dtype, int n_vec, void* x, const void* b, int x_is_zero,
+                const double* lambda, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(x, "x");
+    check_ptr(b, "b");
+    check_dtype(dtype);
+    mfmg::Level& L = ctx->ctx.level(level);
+    MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+    MFMG_REQUIRE(dtype == L.dtype, MFMG_ERR_INVALID_ARG, "dtype must equal the level's storage type");
+    double lmin = L.lmin, lmax = L.lmax;
+    if (lambda) {
+      lmin = lambda[0];
+      lmax = lambda[1];
+      MFMG_REQUIRE(lmax > lmin && lmin > 0, MFMG_ERR_INVALID_ARG, "need 0 < lambda_min < lambda_max");
+    }
+    mfmg::level_smooth(ctx->ctx, level, n_vec, x, b, x_is_zero != 0, lmin, lmax, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_residual(mfmg_ctx ctx, int level, int dtype, int n_vec, void* r, const void* b, const void* x,
+                  void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(r, "r");
+    check_ptr(b, "b");
+    check_ptr(x, "x");
+    check_dtype(dtype);
+    mfmg::Level& L = ctx->ctx.level(level);
+    MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+    MFMG_REQUIRE(dtype == L.dtype, MFMG_ERR_INVALID_ARG, "dtype must equal the level's storage type");
+    mfmg::level_residual(ctx->ctx, level, n_vec, r, b, x, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_prolongate_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* dst_fine, const void* src_coarse,
+                        void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(dst_fine, "dst_fine");
+    check_ptr(src_coarse, "src_coarse");
+    check_dtype(dtype);
+    check_nv(ctx->ctx, n_vec);
+    mfmg::level_prolongate_add(ctx->ctx, fine_level, dtype, n_vec, dst_fine, src_coarse, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* dst_coarse, const void* src_fine,
+                      void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(dst_coarse, "dst_coarse");
+    check_ptr(src_fine, "src_fine");
+    check_dtype(dtype);
+    check_nv(ctx->ctx, n_vec);
+    mfmg::level_restrict_add(ctx->ctx, fine_level, dtype, n_vec, dst_coarse, src_fine, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(x, "x");
+    check_ptr(b, "b");
+    check_dtype(dtype);
+    check_nv(ctx->ctx, n_vec);
+    mfmg::coarse_solve(ctx->ctx, dtype, n_vec, x, b, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(x_f64, "x");
+    check_ptr(b_f64, "b");
+    mfmg::vcycle(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64),
+                 as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_solve(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, double rtol, int max_it, int flexible,
+               mfmg_solve_stats* stats, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(x_f64, "x");
+    check_ptr(b_f64, "b");
+    MFMG_REQUIRE(rtol > 0 && max_it >= 0, MFMG_ERR_INVALID_ARG, "rtol must be > 0, max_it >= 0");
+    int st = mfmg::pcg(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64), rtol,
+                       max_it, flexible != 0, stats, as_stream(stream));
+    if (st == MFMG_ERR_NOT_CONVERGED) g_last_error = "PCG did not converge within max_it";
+    if (st == MFMG_ERR_BREAKDOWN) g_last_error = "PCG breakdown (p^T A p <= 0 or non-finite residual)";
+    return st;
+  });
+}
+
+int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_terms, int n_vec, void* b_f64,
+             void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(b_f64, "b");
+    check_ptr(params, "params");
+    check_nv(ctx->ctx, n_vec);
+    MFMG_REQUIRE(kind == MFMG_RHS_CONST || kind == MFMG_RHS_GAUSS, MFMG_ERR_INVALID_ARG, "rhs kind");
+    MFMG_REQUIRE(kind == MFMG_RHS_CONST || n_terms >= 1, MFMG_ERR_INVALID_ARG, "n_terms");
+    mfmg::Level& L = ctx->ctx.level(level);
+    const size_t np = kind == MFMG_RHS_CONST ? 1 : static_cast<size_t>(n_terms) * 5 * n_vec;
+    mfmg::DeviceArray<double> dp;
+    dp.upload(params, np);
+    mfmg::launch_rhs(L.view, kind, dp.ptr, kind == MFMG_RHS_CONST ? 0 : n_terms, n_vec,
+                     static_cast<double*>(b_f64), as_stream(stream));
+    MFMG_HIP(hipStreamSynchronize(as_stream(stream)));
+    return MFMG_OK;
+  });
+}
+
+}  // extern "C"

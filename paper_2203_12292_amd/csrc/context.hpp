@@ -1,0 +1,75 @@
+// Library state: mesh handle and the multigrid level hierarchy on the GPU.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "dofs.hpp"
+#include "kernels.hpp"
+#include "octree.hpp"
+
+struct mfmg_mesh_s {
+  std::vector<mfmg::Octree> gc;  // global-coarsening sequence, index 0 = coarse grid
+  int64_t n_hanging_fine = 0;
+};
+
+namespace mfmg {
+
+struct Level {
+  int mesh = 0;     // index into the global-coarsening sequence
+  int k = 1;
+  int dtype = MFMG_F64;
+  int64_t n_dofs = 0, n_cells = 0, n_hanging = 0;
+  DeviceArray<int32_t> ent, ijk;
+  DeviceArray<uint32_t> mask;
+  CellView view;
+  DeviceArray<double> diag;
+  DeviceArray<char> dinv;  // 1/diag in the level's arithmetic type
+  double lmin = 0.0, lmax = 1.0;
+  // work vectors (max_rhs interleaved): storage type and arithmetic type
+  DeviceArray<char> x, b, r, d, t, tmp_cast;
+  // transfer from level l-1 (fine side = this level)
+  bool has_transfer = false;
+  DeviceArray<int32_t> tr_ident_c, tr_ident_f, tr_ref_c, tr_ref_f;
+  DeviceArray<uint8_t> tr_valence;
+  TransferView tview;
+};
+
+struct Context {
+  mfmg_level_desc desc{};
+  std::vector<Octree> meshes;
+  std::vector<Level> levels;  // 0 = coarsest
+  int max_rhs = 1;
+  int cheb_degree = 3;
+  // exact coarse solver: dense inverse of A^(0)
+  int64_t n0 = 0;
+  DeviceArray<double> coarse_inv64;
+  DeviceArray<float> coarse_inv32;
+  // FP64 CG work space on the finest level
+  DeviceArray<double> cg_r, cg_p, cg_q, cg_z, cg_zold, cg_partial, cg_scalar;
+  std::vector<double> host_scalar;
+  hipStream_t stream = nullptr;
+
+  Level& fine() { return levels.back(); }
+  Level& level(int l) {
+    MFMG_REQUIRE(l >= 0 && l < static_cast<int>(levels.size()), MFMG_ERR_INVALID_ARG, "level out of range");
+    return levels[l];
+  }
+};
+
+void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc& desc, hipStream_t s);
+
+// operations on levels (all asynchronous on `s` unless noted)
+void level_vmult(Context& ctx, int l, int dtype, int nv, void* dst_acc, const void* src, hipStream_t s);
+void level_smooth(Context& ctx, int l, int nv, void* x, const void* b, bool x_is_zero, double lmin, double lmax,
+                  hipStream_t s);
+void level_residual(Context& ctx, int l, int nv, void* r, const void* b, const void* x, hipStream_t s);
+void level_prolongate_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s);
+void level_restrict_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s);
+void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipStream_t s);
+void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s);
+int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,
+        mfmg_solve_stats* stats, hipStream_t s);
+
+}  // namespace mfmg

@@ -1,0 +1,381 @@
+// DoF numbering, gather maps, transfer categories (host side).
+#include "dofs.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "common.hpp"
+#include "fe1d.hpp"
+#include "slots.hpp"
+
+namespace mfmg {
+
+namespace {
+
+// Interleave the bits of three 21-bit coordinates (Morton / Z order).
+uint64_t spread3(uint64_t x) {
+  x &= 0x1fffff;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | spread3(y) << 1 | spread3(z) << 2; }
+
+// Open-addressing hash map uint64 -> int32 (keys < 2^63).
+struct HashMap {
+  std::vector<uint64_t> keys;
+  std::vector<int32_t> vals;
+  uint64_t mask = 0;
+  explicit HashMap(size_t expected) {
+    size_t cap = 16;
+    while (cap < 2 * expected + 16) cap <<= 1;
+    keys.assign(cap, 0);
+    vals.assign(cap, -1);
+    mask = cap - 1;
+  }
+  static uint64_t mix(uint64_t z) {
+    z ^= z >> 33;
+    z *= 0xff51afd7ed558ccdull;
+    z ^= z >> 33;
+    return z;
+  }
+  // returns existing value or inserts `v`; `inserted` tells which
+  int32_t find_or_insert(uint64_t key, int32_t v, bool& inserted) {
+    const uint64_t tagged = key | (1ull << 63);
+    uint64_t h = mix(key) & mask;
+    while (true) {
+      if (keys[h] == tagged) { inserted = false; return vals[h]; }
+      if (keys[h] == 0) { keys[h] = tagged; vals[h] = v; inserted = true; return v; }
+      h = (h + 1) & mask;
+    }
+  }
+};
+
+// Exact position code of GLL node a of interval i on level l (see mfmg.h).
+int64_t code1d(int l, int64_t i, int a, int k) {
+  if (a == 0) return 2 * (i << (20 - l));
+  if (a == k) return 2 * ((i + 1) << (20 - l));
+  if (k % 2 == 0 && 2 * a == k) return 2 * ((2 * i + 1) << (19 - l));
+  return 2 * ((((static_cast<int64_t>(l) << 25) + i) * 16) + a) + 1;
+}
+
+struct EntityRec {
+  int level;
+  int64_t i, j, k;
+  int slot;
+  int32_t first_dof;
+};
+
+}  // namespace
+
+bool LevelDofs::slot_hanging(int64_t c, int s) const { return mfmg::slot_hanging(mask[c], s); }
+
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet) {
+  MFMG_REQUIRE(k >= 1 && k <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
+  LevelDofs L;
+  L.k = k;
+  L.h0 = (tree.hi - tree.lo) / tree.n0;
+  const int top = tree.n_levels();  // leaves live on levels 0..top
+  MFMG_REQUIRE((static_cast<int64_t>(tree.n0) << top) < (1ll << 19), MFMG_ERR_UNSUPPORTED,
+               "mesh too fine for 21-bit entity coordinates");
+
+  // cells along the Morton curve of their lower corner on the finest lattice
+  std::vector<Cell> cells = tree.leaves();
+  {
+    std::vector<std::pair<uint64_t, int64_t>> order(cells.size());
+    for (size_t c = 0; c < cells.size(); ++c) {
+      const Cell& x = cells[c];
+      int s = top - x.level;
+      order[c] = {morton(x.i << s, x.j << s, x.k << s), static_cast<int64_t>(c)};
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<Cell> sorted(cells.size());
+    for (size_t c = 0; c < cells.size(); ++c) sorted[c] = cells[order[c].second];
+    cells.swap(sorted);
+  }
+  const int64_t nc = static_cast<int64_t>(cells.size());
+  L.n_cells = nc;
+  L.cells = cells;
+  L.mask.assign(nc, 0);
+  L.ent.assign(N_SLOTS * nc, -1);
+  L.ent_id.assign(N_SLOTS * nc, -1);
+
+  // hanging faces / edges on the parent's outer boundary
+  for (int64_t c = 0; c < nc; ++c) {
+    const Cell& x = cells[c];
+    uint32_t m = static_cast<uint32_t>(x.level) << MASK_LEVEL_SHIFT;
+    if (x.level > 0) {
+      const int64_t p[3] = {x.i, x.j, x.k};
+      int s[3], o[3];
+      for (int d = 0; d < 3; ++d) {
+        s[d] = static_cast<int>(p[d] & 1);
+        o[d] = s[d] ? 1 : -1;
+        m |= static_cast<uint32_t>(s[d]) << d;
+      }
+      auto missing = [&](int dx, int dy, int dz) {
+        int64_t a = x.i + dx, b = x.j + dy, cc = x.k + dz;
+        if (!tree.inside(x.level, a, b, cc) || tree.exists(x.level, a, b, cc)) return false;
+        MFMG_REQUIRE(tree.exists(x.level - 1, a >> 1, b >> 1, cc >> 1), MFMG_ERR_INVALID_ARG,
+                     "mesh is not one-irregular");
+        return true;
+      };
+      for (int d = 0; d < 3; ++d) {
+        int off[3] = {0, 0, 0};
+        off[d] = o[d];
+        if (missing(off[0], off[1], off[2])) m |= 1u << (MASK_FACE_SHIFT + d);
+      }
+      for (int d = 0; d < 3; ++d) {
+        const int e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;
+        int a1[3] = {0, 0, 0}, a2[3] = {0, 0, 0}, a3[3] = {0, 0, 0};
+        a1[e] = o[e];
+        a2[f] = o[f];
+        a3[e] = o[e];
+        a3[f] = o[f];
+        if (missing(a1[0], a1[1], a1[2]) || missing(a2[0], a2[1], a2[2]) || missing(a3[0], a3[1], a3[2]))
+          m |= 1u << (MASK_EDGE_SHIFT + d);
+      }
+    }
+    L.mask[c] = m;
+    if (mask_hanging(m)) ++L.n_hanging_cells;
+  }
+
+  // entities: numbering in first-touch order
+  const int64_t dmax = static_cast<int64_t>(2 * tree.n0) << top;
+  HashMap map(static_cast<size_t>(nc) * 8 + 64);
+  std::vector<EntityRec> ents;
+  ents.reserve(static_cast<size_t>(nc) * 8);
+  int64_t next = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    const Cell& x = cells[c];
+    const uint32_t m = L.mask[c];
+    for (int s = 0; s < 26; ++s) {
+      Cell owner = x;
+      if (mfmg::slot_hanging(m, s)) owner = {x.level - 1, x.i >> 1, x.j >> 1, x.k >> 1};
+      const int sh = top - owner.level;
+      int64_t D[3];
+      const int64_t q[3] = {owner.i, owner.j, owner.k};
+      bool boundary = false;
+      for (int d = 0; d < 3; ++d) {
+        const int sd = slot_side(s, d);
+        D[d] = sd < 0 ? (2 * q[d] + 1) << sh : (2 * (q[d] + sd)) << sh;
+        if (sd >= 0 && (D[d] == 0 || D[d] == dmax)) boundary = true;
+      }
+      if (dirichlet && boundary) continue;
+      const uint64_t key = (static_cast<uint64_t>(D[0]) << 42) | (static_cast<uint64_t>(D[1]) << 21) |
+                           static_cast<uint64_t>(D[2]);
+      bool inserted;
+      int32_t id = map.find_or_insert(key, static_cast<int32_t>(ents.size()), inserted);
+      if (inserted) {
+        ents.push_back({owner.level, owner.i, owner.j, owner.k, s, static_cast<int32_t>(next)});
+        next += slot_size(s, k);
+        MFMG_REQUIRE(next < (1ll << 31), MFMG_ERR_UNSUPPORTED, "more than 2^31 DoFs on a level");
+      }
+      L.ent[s * nc + c] = ents[id].first_dof;
+      L.ent_id[s * nc + c] = id;
+    }
+  }
+  L.n_shared = next;
+  const int64_t nint = static_cast<int64_t>(k - 1) * (k - 1) * (k - 1);
+  MFMG_REQUIRE(next + nint * nc < (1ll << 31), MFMG_ERR_UNSUPPORTED, "more than 2^31 DoFs on a level");
+  for (int64_t c = 0; c < nc; ++c) {
+    L.ent[26 * nc + c] = static_cast<int32_t>(next + nint * c);
+    L.ent_id[26 * nc + c] = static_cast<int32_t>(ents.size() + c);
+  }
+  L.n_dofs = next + nint * nc;
+  L.n_entities = static_cast<int64_t>(ents.size()) + nc;
+
+  // exact node codes of every DoF
+  L.codes.assign(3 * L.n_dofs, 0);
+  auto emit = [&](int lv, int64_t ci, int64_t cj, int64_t ck, int s, int64_t first) {
+    int64_t dof = first;
+    const int sa = slot_side(s, 0), sb = slot_side(s, 1), sc = slot_side(s, 2);
+    for (int c = (sc < 0 ? 1 : sc * k); c <= (sc < 0 ? k - 1 : sc * k); ++c)
+      for (int b = (sb < 0 ? 1 : sb * k); b <= (sb < 0 ? k - 1 : sb * k); ++b)
+        for (int a = (sa < 0 ? 1 : sa * k); a <= (sa < 0 ? k - 1 : sa * k); ++a) {
+          L.codes[3 * dof + 0] = code1d(lv, ci, a, k);
+          L.codes[3 * dof + 1] = code1d(lv, cj, b, k);
+          L.codes[3 * dof + 2] = code1d(lv, ck, c, k);
+          ++dof;
+        }
+  };
+  for (const EntityRec& e : ents) emit(e.level, e.i, e.j, e.k, e.slot, e.first_dof);
+  for (int64_t c = 0; c < nc; ++c) emit(cells[c].level, cells[c].i, cells[c].j, cells[c].k, 26, next + nint * c);
+  return L;
+}
+
+TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial) {
+  TransferDofs T;
+  T.polynomial = polynomial;
+  const int64_t nf = fine.n_cells, ncc = coarse.n_cells;
+  // groups of fine cells, one per coarse cell
+  std::vector<int64_t> group_start(ncc + 1, 0);
+  std::vector<int32_t> group_cells;
+  group_cells.reserve(nf);
+  if (polynomial) {
+    MFMG_REQUIRE(nf == ncc, MFMG_ERR_INVALID_ARG, "polynomial transfer needs equal meshes");
+    for (int64_t c = 0; c < ncc; ++c) {
+      const Cell &a = fine.cells[c], &b = coarse.cells[c];
+      MFMG_REQUIRE(a.level == b.level && a.i == b.i && a.j == b.j && a.k == b.k, MFMG_ERR_INVALID_ARG,
+                   "polynomial transfer needs equal meshes");
+      T.ident_coarse.push_back(static_cast<int32_t>(c));
+      T.ident_fine.push_back(static_cast<int32_t>(c));
+      group_cells.push_back(static_cast<int32_t>(c));
+      group_start[c + 1] = group_start[c] + 1;
+    }
+  } else {
+    // lookup of fine cells by (level, key)
+    std::vector<std::pair<uint64_t, int32_t>> idx(nf);
+    for (int64_t c = 0; c < nf; ++c) {
+      const Cell& x = fine.cells[c];
+      idx[c] = {(static_cast<uint64_t>(x.level) << 59) ^ cell_key(x.i, x.j, x.k), static_cast<int32_t>(c)};
+    }
+    std::sort(idx.begin(), idx.end());
+    auto find = [&](int l, int64_t i, int64_t j, int64_t k) -> int32_t {
+      uint64_t key = (static_cast<uint64_t>(l) << 59) ^ cell_key(i, j, k);
+      auto it = std::lower_bound(idx.begin(), idx.end(), std::make_pair(key, static_cast<int32_t>(-1)));
+      if (it != idx.end() && it->first == key) return it->second;
+      return -1;
+    };
+    for (int64_t c = 0; c < ncc; ++c) {
+      const Cell& x = coarse.cells[c];
+      int32_t f = find(x.level, x.i, x.j, x.k);
+      if (f >= 0) {
+        T.ident_coarse.push_back(static_cast<int32_t>(c));
+        T.ident_fine.push_back(f);
+        group_cells.push_back(f);
+      } else {
+        T.refined_coarse.push_back(static_cast<int32_t>(c));
+        for (int ch = 0; ch < 8; ++ch) {
+          int32_t g = find(x.level + 1, 2 * x.i + (ch & 1), 2 * x.j + ((ch >> 1) & 1), 2 * x.k + ((ch >> 2) & 1));
+          MFMG_REQUIRE(g >= 0, MFMG_ERR_INVALID_ARG, "fine mesh is not a refinement of the coarse mesh");
+          group_cells.push_back(g);
+        }
+      }
+      group_start[c + 1] = static_cast<int64_t>(group_cells.size());
+    }
+    const int64_t nr = static_cast<int64_t>(T.refined_coarse.size());
+    T.refined_fine.assign(8 * nr, -1);
+    int64_t r = 0;
+    for (int64_t c = 0; c < ncc; ++c)
+      if (group_start[c + 1] - group_start[c] == 8) {
+        for (int ch = 0; ch < 8; ++ch) T.refined_fine[ch * nr + r] = group_cells[group_start[c] + ch];
+        ++r;
+      }
+  }
+  MFMG_REQUIRE(static_cast<int64_t>(group_cells.size()) == nf, MFMG_ERR_INVALID_ARG,
+               "transfer groups do not cover the fine mesh");
+
+  // valence: number of groups in which an entity appears unconstrained
+  std::vector<uint8_t> count(fine.n_entities, 0);
+  std::vector<int32_t> seen;
+  for (int64_t g = 0; g < ncc; ++g) {
+    seen.clear();
+    for (int64_t q = group_start[g]; q < group_start[g + 1]; ++q) {
+      const int32_t c = group_cells[q];
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = fine.ent_id[s * nf + c];
+        if (id < 0 || fine.slot_hanging(c, s)) continue;
+        seen.push_back(id);
+      }
+    }
+    std::sort(seen.begin(), seen.end());
+    seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+    for (int32_t id : seen) {
+      MFMG_REQUIRE(count[id] < 255, MFMG_ERR_INVALID_ARG, "valence overflow");
+      ++count[id];
+    }
+  }
+  T.valence.assign(N_SLOTS * nf, 0);
+  for (int64_t c = 0; c < nf; ++c)
+    for (int s = 0; s < N_SLOTS; ++s) {
+      const int32_t id = fine.ent_id[s * nf + c];
+      if (id < 0 || fine.slot_hanging(c, s)) continue;
+      MFMG_REQUIRE(count[id] > 0, MFMG_ERR_INVALID_ARG, "entity without a transfer group");
+      T.valence[s * nf + c] = count[id];
+    }
+  return T;
+}
+
+namespace {
+// apply the hanging-node interpolation (or its transpose) to a cell vector
+void apply_constraints_host(std::vector<double>& u, uint32_t m, const Tables1D& t, bool transpose) {
+  const int n = t.n, k = t.k;
+  std::vector<double> line(n), out(n);
+  for (int d = 0; d < 3; ++d) {
+    const int sd = mask_sub(m, d);
+    const std::vector<double>& H = t.H[sd];
+    for (int q = 0; q < n; ++q)
+      for (int p = 0; p < n; ++p) {
+        if (!hanging_line(m, d, p, q, k)) continue;
+        auto idx = [&](int r) {
+          int a = d == 0 ? r : p, b = d == 0 ? p : d == 1 ? r : q, c = d == 2 ? r : q;
+          return a + n * b + n * n * c;
+        };
+        for (int r = 0; r < n; ++r) line[r] = u[idx(r)];
+        for (int r = 0; r < n; ++r) {
+          double s = 0;
+          for (int r2 = 0; r2 < n; ++r2) s += transpose ? H[r2 * n + r] * line[r2] : H[r * n + r2] * line[r2];
+          out[r] = s;
+        }
+        for (int r = 0; r < n; ++r) u[idx(r)] = out[r];
+      }
+  }
+}
+}  // namespace
+
+std::vector<double> assemble_dense(const LevelDofs& L, const Tables1D& t) {
+  const int n = t.n, k = t.k, n3 = n * n * n;
+  const int64_t N = L.n_dofs;
+  std::vector<double> A(static_cast<size_t>(N * N), 0.0);
+  std::vector<double> Ae(static_cast<size_t>(n3) * n3), C(static_cast<size_t>(n3) * n3), col(n3),
+      tmp(static_cast<size_t>(n3) * n3);
+  std::vector<int64_t> dof(n3);
+  for (int64_t c = 0; c < L.n_cells; ++c) {
+    const uint32_t m = L.mask[c];
+    const double h = L.h0 * std::ldexp(1.0, -mask_level(m));
+    for (int i = 0; i < n3; ++i)
+      for (int j = 0; j < n3; ++j) {
+        int a = i % n, b = (i / n) % n, cc = i / (n * n);
+        int a2 = j % n, b2 = (j / n) % n, c2 = j / (n * n);
+        Ae[i * n3 + j] = h * (t.K[a * n + a2] * t.M[b * n + b2] * t.M[cc * n + c2] +
+                              t.M[a * n + a2] * t.K[b * n + b2] * t.M[cc * n + c2] +
+                              t.M[a * n + a2] * t.M[b * n + b2] * t.K[cc * n + c2]);
+      }
+    // C (columns = constraint interpolation of unit slot vectors)
+    for (int j = 0; j < n3; ++j) {
+      std::fill(col.begin(), col.end(), 0.0);
+      col[j] = 1.0;
+      apply_constraints_host(col, m, t, false);
+      for (int i = 0; i < n3; ++i) C[i * n3 + j] = col[i];
+    }
+    for (int i = 0; i < n3; ++i) {
+      int a = i % n, b = (i / n) % n, cc = i / (n * n);
+      int s = node_slot(a, b, cc, k);
+      int32_t e = L.ent[s * L.n_cells + c];
+      dof[i] = e < 0 ? -1 : static_cast<int64_t>(e) + node_offset(a, b, cc, k);
+    }
+    // tmp = Ae C ; local = C^T tmp
+    for (int i = 0; i < n3; ++i)
+      for (int j = 0; j < n3; ++j) {
+        double s = 0;
+        for (int q = 0; q < n3; ++q) s += Ae[i * n3 + q] * C[q * n3 + j];
+        tmp[i * n3 + j] = s;
+      }
+    for (int i = 0; i < n3; ++i) {
+      if (dof[i] < 0) continue;
+      for (int j = 0; j < n3; ++j) {
+        if (dof[j] < 0) continue;
+        double s = 0;
+        for (int q = 0; q < n3; ++q) s += C[q * n3 + i] * tmp[q * n3 + j];
+        A[dof[i] * N + dof[j]] += s;
+      }
+    }
+  }
+  return A;
+}
+
+}  // namespace mfmg

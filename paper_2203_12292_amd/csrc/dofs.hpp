@@ -1,0 +1,82 @@
+// Degrees of freedom of a multigrid level and the per-cell data of the
+// matrix-free loops (host side).
+//
+// Numbering.  A Q_k DoF belongs to one geometric entity of the mesh: a
+// vertex, an edge (k-1 DoFs), a face ((k-1)^2) or a cell interior ((k-1)^3).
+// Entities on the domain boundary carry homogeneous Dirichlet constraints and
+// have no DoFs.  Entities are identified by the doubled coordinates of their
+// centre on the finest lattice (unique across levels).  DoFs of vertices,
+// edges and faces ("shared" DoFs) are numbered first, entity by entity in the
+// order the cells (sorted along the Morton curve) first touch them; cell
+// interiors follow, cell by cell.
+//
+// Gather maps with hanging-node constraints (Section 3.2: constraints applied
+// while the DoF values are set up, via an updated DoF map and in-place 1D
+// interpolation).  A cell of level l >= 1 that is child (sx, sy, sz) of its
+// parent can only have hanging faces and edges on the parent's outer
+// boundary: the face normal to axis d on side s_d, and the edge parallel to
+// axis d through the corner (s_x, s_y, s_z).  For each of the 27 entity slots
+// of the cell (8 vertices, 12 edges, 6 faces, interior) the map stores the
+// first DoF index of the entity, or -1 for a Dirichlet entity.  Slots lying in
+// a hanging face or on a hanging edge point to the *parent's* entity of the
+// same slot (the coarse neighbour's face, edge or vertex at the same relative
+// position); the kernels then interpolate the gathered coarse values in place
+// along the lines of the hanging faces/edges.  The mask of a cell holds
+// bits 0-2 (sx, sy, sz), 3-5 (hanging face x, y, z), 6-8 (hanging edge
+// x, y, z) and the cell level in bits 16-23.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "octree.hpp"
+
+namespace mfmg {
+
+enum : uint32_t {
+  MASK_FACE_SHIFT = 3,
+  MASK_EDGE_SHIFT = 6,
+  MASK_LEVEL_SHIFT = 16,
+};
+
+constexpr int N_SLOTS = 27;
+
+struct LevelDofs {
+  int k = 1;
+  int64_t n_cells = 0;
+  int64_t n_dofs = 0;
+  int64_t n_shared = 0;
+  int64_t n_hanging_cells = 0;
+  double h0 = 1.0;                // coarse-grid cell size (level-0)
+  std::vector<Cell> cells;        // Morton order
+  std::vector<int32_t> ent;       // [N_SLOTS][n_cells] first DoF of the slot's entity, -1 Dirichlet
+  std::vector<int32_t> ent_id;    // [N_SLOTS][n_cells] entity id (-1 Dirichlet), interior included
+  std::vector<uint32_t> mask;     // per cell
+  std::vector<int64_t> codes;     // [n_dofs][3]
+  int64_t n_entities = 0;
+  bool slot_hanging(int64_t c, int s) const;
+};
+
+// Builds the DoF numbering and gather maps of `tree` at degree k.
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet);
+
+// Transfer data between a fine level and the next coarser one (Section 3.5).
+// Geometric: every coarse cell is a fine cell (identity category) or the
+// parent of 8 fine cells (refinement category).  Polynomial: same cells,
+// one category.  valence[slot][fine cell] = number of transfer groups (coarse
+// cells) in which the slot's entity appears unconstrained; 0 for constrained
+// (hanging or Dirichlet) slots.  The prolongation weights are 1/valence.
+struct TransferDofs {
+  bool polynomial = false;
+  std::vector<int32_t> ident_coarse, ident_fine;   // identity category pairs
+  std::vector<int32_t> refined_coarse;             // refinement category coarse cells
+  std::vector<int32_t> refined_fine;               // [8][n_refined] children, child c = sx + 2 sy + 4 sz
+  std::vector<uint8_t> valence;                    // [N_SLOTS][n_fine_cells]
+};
+
+TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial);
+
+// Dense assembled matrix of a (small) level: sum_e C_e^T A_e C_e.
+std::vector<double> assemble_dense(const LevelDofs& L, const struct Tables1D& t);
+
+}  // namespace mfmg

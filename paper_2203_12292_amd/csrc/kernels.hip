@@ -1,0 +1,1177 @@
+// Device kernels of the matrix-free multigrid hot path (CDNA4 / gfx950).
+//
+// Cell operator (Eq. impl:mf): v = sum_e G_e^T C_e^T S_e^T Q_e S_e C_e G_e x.
+// Every cell is an axis-aligned cube of side h, so the quadrature-point
+// operation Q_e reduces to the scalar h * w_q and the cell matrix has the
+// tensor form h (K (x) M (x) M + M (x) K (x) M + M (x) M (x) K) with the 1D
+// mass M and stiffness K integrated exactly by the (k+1)-point Gauss rule.
+// The kernel applies it as seven 1D sweeps: M_x/K_x, then M_y/K_y, then
+// M_z/K_z (fewer contractions than interpolating to quadrature points and
+// back, same result up to rounding).
+//
+// Thread layout: n^2 threads per cell (n = k+1), each owning one line of n
+// nodes; a block holds CPB cells.  A phase works on lines along one axis in
+// registers; LDS re-distributes the cell's n^3 values between phases.
+// Hanging-node constraints (Section 3.2, the in-place interpolation variant)
+// are 1D interpolations along the lines of the hanging faces/edges, applied
+// in the phase whose lines run along that axis: gather + z, y, x before the
+// operator, transposed z, x, y after it, then the scatter.
+#include "common.hpp"
+#include "fe1d.hpp"
+#include "kernels.hpp"
+#include "slots.hpp"
+
+namespace mfmg {
+
+// ---------------------------------------------------------------------------
+// tables passed by value as kernel arguments (scalar-loaded)
+template <typename T, int N>
+struct OpTab {
+  T M[N * N];
+  T K[N * N];
+  T H[2][N * N];
+};
+
+template <typename T, int NF, int NC>
+struct TrTab {
+  T P[NF * NC];     // 1D prolongation, row-major NF x NC
+  T H[2][NC * NC];  // hanging interpolation of the coarse cell
+};
+
+template <int N>
+struct Gauss1D {
+  double x[N];      // Gauss points on [0, 1]
+  double w[N];      // weights
+  double S[N * N];  // S[q*N + i] = l_i(x_q)
+};
+
+template <int N> struct CPBOf { static constexpr int v = 1; };
+template <> struct CPBOf<2> { static constexpr int v = 64; };
+template <> struct CPBOf<3> { static constexpr int v = 28; };
+template <> struct CPBOf<4> { static constexpr int v = 16; };
+template <> struct CPBOf<5> { static constexpr int v = 10; };
+template <> struct CPBOf<6> { static constexpr int v = 7; };
+template <> struct CPBOf<7> { static constexpr int v = 5; };
+
+inline const Tables1D& tables(int k) {
+  static Tables1D t[7] = {Tables1D(1), Tables1D(1), Tables1D(2), Tables1D(3),
+                          Tables1D(4), Tables1D(5), Tables1D(6)};
+  return t[k];
+}
+
+template <int N>
+Gauss1D<N> make_gauss() {
+  const Tables1D& t = tables(N - 1);
+  Gauss1D<N> g;
+  for (int i = 0; i < N; ++i) {
+    g.x[i] = t.qp[i];
+    g.w[i] = t.qw[i];
+  }
+  for (int i = 0; i < N * N; ++i) g.S[i] = t.S[i];
+  return g;
+}
+
+template <typename T, int N>
+OpTab<T, N> make_optab() {
+  const Tables1D& t = tables(N - 1);
+  OpTab<T, N> o;
+  for (int i = 0; i < N * N; ++i) {
+    o.M[i] = static_cast<T>(t.M[i]);
+    o.K[i] = static_cast<T>(t.K[i]);
+    o.H[0][i] = static_cast<T>(t.H[0][i]);
+    o.H[1][i] = static_cast<T>(t.H[1][i]);
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// small dense 1D contractions on register arrays
+template <int N, typename T>
+__device__ __forceinline__ void mv(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = A[i * N] * x[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) s += A[i * N + j] * x[j];
+    y[i] = s;
+  }
+}
+
+// y = A x + B z (A, B symmetric use)
+template <int N, typename T>
+__device__ __forceinline__ void mv2(const T* __restrict__ A, const T (&x)[N], const T* __restrict__ B,
+                                    const T (&z)[N], T (&y)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = A[i * N] * x[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) s += A[i * N + j] * x[j];
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += B[i * N + j] * z[j];
+    y[i] = s;
+  }
+}
+
+// in-place hanging interpolation u <- H_s u (transpose: u <- H_s^T u)
+template <int N, typename T, bool TRANS>
+__device__ __forceinline__ void interp(const T (&H)[2][N * N], int s, T (&u)[N]) {
+  T out[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int idx = TRANS ? j * N + i : i * N + j;
+      const T h = s ? H[1][idx] : H[0][idx];
+      acc += h * u[j];
+    }
+    out[i] = acc;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = out[i];
+}
+
+template <typename T> __device__ __forceinline__ void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+
+// bfloat16 add through a compare-and-swap on the enclosing 32-bit word
+// (used only on the small levels stored in bfloat16)
+__device__ __forceinline__ void atomic_add_bf16(bf16* p, float v) {
+  uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+  unsigned int* word = reinterpret_cast<unsigned int*>(addr & ~uintptr_t(3));
+  const unsigned int shift = (addr & 2) ? 16u : 0u;
+  unsigned int old = *word, assumed;
+  do {
+    assumed = old;
+    bf16 cur;
+    cur.bits = static_cast<uint16_t>((assumed >> shift) & 0xffffu);
+    bf16 nv = float_to_bf16(bf16_to_float(cur) + v);
+    unsigned int repl = (assumed & ~(0xffffu << shift)) | (static_cast<unsigned int>(nv.bits) << shift);
+    old = atomicCAS(word, assumed, repl);
+  } while (old != assumed);
+}
+
+// dst += v for a storage-typed vector entry; `exclusive` entries have no
+// concurrent writer and use a plain read-modify-write.
+template <typename S, typename T>
+__device__ __forceinline__ void add_to(S* p, T v, bool exclusive) {
+  if (exclusive) {
+    *p = store_as<S>(load_as<T>(*p) + v);
+  } else {
+    if constexpr (sizeof(S) == 2) atomic_add_bf16(reinterpret_cast<bf16*>(p), static_cast<float>(v));
+    else atomic_add(p, static_cast<S>(v));
+  }
+}
+
+// gather of the line of nodes (a, b, 0..k) (along z), constraints not yet applied
+template <int K, typename S, typename T>
+__device__ __forceinline__ void gather_zline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell,
+                                             int a, int b, const S* __restrict__ src, int nv, int v,
+                                             T (&u)[K + 1]) {
+  const int s0 = node_slot(a, b, 0, K), s1 = node_slot(a, b, K, K);
+  const int o0 = node_offset(a, b, 0, K);
+  const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
+  u[0] = e0 < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e0 + o0) * nv + v]);
+  u[K] = e1 < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e1 + o0) * nv + v]);
+  if constexpr (K > 1) {
+    const int sm = node_slot(a, b, 1, K);
+    const int om = node_offset(a, b, 1, K);
+    const int st = K > 2 ? node_offset(a, b, 2, K) - om : 0;
+    const int32_t em = ent[sm * nc + cell];
+#pragma unroll
+    for (int c = 1; c < K; ++c)
+      u[c] = em < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(em + om + (c - 1) * st) * nv + v]);
+  }
+}
+
+// scatter-add of the line of nodes (a, 0..k, c) (along y); cell interiors are
+// owned by the cell (plain store), shared entities use atomics.
+template <int K, typename T>
+__device__ __forceinline__ void scatter_yline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell,
+                                              int a, int c, const T (&w)[K + 1], T* __restrict__ dst, int nv,
+                                              int v) {
+  const int s0 = node_slot(a, 0, c, K), s1 = node_slot(a, K, c, K);
+  const int o0 = node_offset(a, 0, c, K);
+  const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
+  if (e0 >= 0) atomic_add(&dst[static_cast<int64_t>(e0 + o0) * nv + v], w[0]);
+  if (e1 >= 0) atomic_add(&dst[static_cast<int64_t>(e1 + o0) * nv + v], w[K]);
+  if constexpr (K > 1) {
+    const int sm = node_slot(a, 1, c, K);
+    const int om = node_offset(a, 1, c, K);
+    const int st = K > 2 ? node_offset(a, 2, c, K) - om : 0;
+    const int32_t em = ent[sm * nc + cell];
+    if (em >= 0) {
+      if (sm == 26) {
+#pragma unroll
+        for (int b = 1; b < K; ++b) dst[static_cast<int64_t>(em + om + (b - 1) * st) * nv + v] = w[b];
+      } else {
+#pragma unroll
+        for (int b = 1; b < K; ++b) atomic_add(&dst[static_cast<int64_t>(em + om + (b - 1) * st) * nv + v], w[b]);
+      }
+    }
+  }
+}
+
+// The cell pipeline C^T S^T Q S C on the block's LDS.  Input: this thread's
+// z-line (x = ta, y = tb) of gathered slot values.  Output: this thread's
+// y-line (x = ta, z = tb) of the result, before the scatter.  Must be called
+// by all threads of the block (contains barriers).
+template <int K, typename T>
+__device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict__ B1, bool active, uint32_t m,
+                                              int block_hang, T h, const OpTab<T, K + 1>& tab, int ta, int tb,
+                                              T (&u)[K + 1]) {
+  constexpr int N = K + 1, N2 = N * N;
+  const bool hang = mask_hanging(m);
+  // phase 1: z-lines (x = ta, y = tb): hanging z-interpolation, store
+  if (active) {
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp<N, T, false>(tab.H, mask_sub(m, 2), u);
+#pragma unroll
+    for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];
+  }
+  __syncthreads();
+  // phase 2: y-lines (x = ta, z = tb): hanging y-interpolation
+  if (block_hang) {
+    if (active && hang && hanging_line(m, 1, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
+      interp<N, T, false>(tab.H, mask_sub(m, 1), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
+    }
+    __syncthreads();
+  }
+  // phase 3: x-lines (y = ta, z = tb): hanging x-interpolation, M_x, K_x
+  T a[N], b[N];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
+    if (hang && hanging_line(m, 0, ta, tb, K)) interp<N, T, false>(tab.H, mask_sub(m, 0), u);
+    mv<N>(tab.M, u, a);
+    mv<N>(tab.K, u, b);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      B0[tb * N2 + ta * N + r] = a[r];
+      B1[tb * N2 + ta * N + r] = b[r];
+    }
+  }
+  __syncthreads();
+  // phase 4: y-lines (x = ta, z = tb): M_y a ; K_y a + M_y b
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      a[r] = B0[tb * N2 + r * N + ta];
+      b[r] = B1[tb * N2 + r * N + ta];
+    }
+    T c1[N], f[N];
+    mv<N>(tab.M, a, c1);
+    mv2<N>(tab.K, a, tab.M, b, f);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      B0[tb * N2 + r * N + ta] = c1[r];
+      B1[tb * N2 + r * N + ta] = f[r];
+    }
+  }
+  __syncthreads();
+  // phase 5: z-lines (x = ta, y = tb): h (K_z c + M_z f), transposed z-interpolation
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      a[r] = B0[r * N2 + tb * N + ta];
+      b[r] = B1[r * N2 + tb * N + ta];
+    }
+    mv2<N>(tab.K, a, tab.M, b, u);
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] *= h;
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp<N, T, true>(tab.H, mask_sub(m, 2), u);
+#pragma unroll
+    for (int r = 0; r < N; ++r) B0[r * N2 + tb * N + ta] = u[r];
+  }
+  __syncthreads();
+  // phase 6: x-lines (y = ta, z = tb): transposed x-interpolation
+  if (block_hang) {
+    if (active && hang && hanging_line(m, 0, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
+      interp<N, T, true>(tab.H, mask_sub(m, 0), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
+    }
+    __syncthreads();
+  }
+  // phase 7: y-lines (x = ta, z = tb): transposed y-interpolation
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
+    if (hang && hanging_line(m, 1, ta, tb, K)) interp<N, T, true>(tab.H, mask_sub(m, 1), u);
+  }
+}
+
+template <int K, typename S, typename T>
+__global__ void __launch_bounds__(CPBOf<K + 1>::v * (K + 1) * (K + 1))
+    vmult_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc, double h0,
+                 OpTab<T, K + 1> tab, const S* __restrict__ src, T* __restrict__ dst, int nv) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPB = CPBOf<N>::v;
+  __shared__ T buf0[CPB * N3];
+  __shared__ T buf1[CPB * N3];
+  const int v = blockIdx.y;
+  const int lc = threadIdx.x / N2;
+  const int t = threadIdx.x - lc * N2;
+  const int ta = t % N, tb = t / N;
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * CPB + lc;
+  const bool active = cell < nc;
+  const uint32_t m = active ? mask[cell] : 0u;
+  const int block_hang = __syncthreads_or(mask_hanging(m) ? 1 : 0);
+  const T h = static_cast<T>(ldexp(h0, -mask_level(m)));
+  T u[N];
+  if (active) gather_zline<K>(ent, nc, cell, ta, tb, src, nv, v, u);
+  cell_pipeline<K, T>(buf0 + lc * N3, buf1 + lc * N3, active, m, block_hang, h, tab, ta, tb, u);
+  if (active) scatter_yline<K>(ent, nc, cell, ta, tb, u, dst, nv, v);
+}
+
+// Diagonal (Eq. impl:mf:diagonal).  Cells without constraints: d_e(i) =
+// A_e(i,i) = h (K_aa M_bb M_cc + M_aa K_bb M_cc + M_aa M_bb K_cc).  Cells with
+// hanging nodes: apply C_e^T A_e C_e to every unit slot vector e_s and keep
+// entry s.  One cell per block, n^2 threads.
+template <int K>
+__global__ void __launch_bounds__((K + 1) * (K + 1))
+    diag_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc, double h0,
+                OpTab<double, K + 1> tab, double* __restrict__ diag) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
+  __shared__ double B0[N3];
+  __shared__ double B1[N3];
+  const int64_t cell = blockIdx.x;
+  const int ta = threadIdx.x % N, tb = threadIdx.x / N;
+  const uint32_t m = mask[cell];
+  const double h = ldexp(h0, -mask_level(m));
+  double d[N];  // y-line (x = ta, z = tb)
+  if (!mask_hanging(m)) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+      d[r] = h * (tab.K[ta * N + ta] * tab.M[r * N + r] * tab.M[tb * N + tb] +
+                  tab.M[ta * N + ta] * tab.K[r * N + r] * tab.M[tb * N + tb] +
+                  tab.M[ta * N + ta] * tab.M[r * N + r] * tab.K[tb * N + tb]);
+  } else {
+    for (int r = 0; r < N; ++r) d[r] = 0.0;
+    for (int s = 0; s < N3; ++s) {
+      const int sa = s % N, sb = (s / N) % N, sc = s / N2;
+      double u[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) u[c] = (ta == sa && tb == sb && c == sc) ? 1.0 : 0.0;
+      cell_pipeline<K, double>(B0, B1, true, m, 1, h, tab, ta, tb, u);
+      if (ta == sa && tb == sc) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+          if (r == sb) d[r] += u[r];
+      }
+      __syncthreads();
+    }
+  }
+  scatter_yline<K>(ent, nc, cell, ta, tb, d, diag, 1, 0);
+}
+
+// Load vector b_e = int_e f phi (Gauss (k+1)^3), then C_e^T and scatter.
+// One cell per block, n^2 threads; f = const or a sum of Gaussians.
+template <int K>
+__global__ void __launch_bounds__((K + 1) * (K + 1))
+    rhs_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask,
+               const int32_t* __restrict__ cell_ijk, int64_t nc, double h0, double lo, OpTab<double, K + 1> tab,
+               Gauss1D<K + 1> g, int kind, const double* __restrict__ params, int n_terms, double* __restrict__ b,
+               int nv) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
+  __shared__ double B0[N3];
+  const int64_t cell = blockIdx.x;
+  const int v = blockIdx.y;
+  const int ta = threadIdx.x % N, tb = threadIdx.x / N;
+  const uint32_t m = mask[cell];
+  const int lev = mask_level(m);
+  const double h = ldexp(h0, -lev);
+  const double x0 = lo + h * cell_ijk[3 * cell + 0];
+  const double y0 = lo + h * cell_ijk[3 * cell + 1];
+  const double z0 = lo + h * cell_ijk[3 * cell + 2];
+  // z-line of quadrature points (qx = ta, qy = tb): weighted f values
+  double gz[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double x = x0 + h * g.x[ta], y = y0 + h * g.x[tb], z = z0 + h * g.x[q];
+    double f = 0.0;
+    if (kind == 0) {
+      f = params[0];
+    } else {
+      const double* p = params + static_cast<int64_t>(v) * n_terms * 5;
+      for (int t = 0; t < n_terms; ++t) {
+        double dx = x - p[5 * t], dy = y - p[5 * t + 1], dz = z - p[5 * t + 2], w = p[5 * t + 3];
+        f += p[5 * t + 4] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * w * w));
+      }
+    }
+    gz[q] = f * g.w[ta] * g.w[tb] * g.w[q] * h * h * h;
+  }
+  // S^T along z: out[c] = sum_q S[q][c] gz[q]
+  double u[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += g.S[q * N + c] * gz[q];
+    u[c] = s;
+  }
+#pragma unroll
+  for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];  // (qx, qy, c)
+  __syncthreads();
+  // along y at (qx = ta, c = tb)
+#pragma unroll
+  for (int r = 0; r < N; ++r) gz[r] = B0[tb * N2 + r * N + ta];
+#pragma unroll
+  for (int bb = 0; bb < N; ++bb) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += g.S[q * N + bb] * gz[q];
+    u[bb] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];  // (qx, b, c)
+  __syncthreads();
+  // along x at (b = ta, c = tb)
+#pragma unroll
+  for (int r = 0; r < N; ++r) gz[r] = B0[tb * N2 + ta * N + r];
+#pragma unroll
+  for (int aa = 0; aa < N; ++aa) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += g.S[q * N + aa] * gz[q];
+    u[aa] = s;
+  }
+  const bool hang = mask_hanging(m);
+  if (hang && hanging_line(m, 0, ta, tb, K)) interp<N, double, true>(tab.H, mask_sub(m, 0), u);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];  // (a, b, c)
+  __syncthreads();
+  // z-lines (x = ta, y = tb): transposed z
+#pragma unroll
+  for (int r = 0; r < N; ++r) u[r] = B0[r * N2 + tb * N + ta];
+  if (hang && hanging_line(m, 2, ta, tb, K)) interp<N, double, true>(tab.H, mask_sub(m, 2), u);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[r * N2 + tb * N + ta] = u[r];
+  __syncthreads();
+  // y-lines (x = ta, z = tb): transposed y, scatter
+#pragma unroll
+  for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
+  if (hang && hanging_line(m, 1, ta, tb, K)) interp<N, double, true>(tab.H, mask_sub(m, 1), u);
+  scatter_yline<K>(ent, nc, cell, ta, tb, u, b, nv, v);
+}
+
+}  // namespace mfmg
+
+namespace mfmg {
+
+// ---------------------------------------------------------------------------
+// Intergrid transfer (Section 3.5, Eq. eq:impl:loop:categorized): one coarse
+// cell (transfer group) per block of 64 threads.  Prolongation:
+//   coarse gather G_c with constraints C_c (in-place interpolation),
+//   category prolongation P (three 1D sweeps; identity category: none),
+//   weights W = 1/valence (0 for constrained fine DoFs), scatter S_f.
+// Restriction is the transpose of every step.
+//
+// Lattice of a group: NF nodes per axis.  Refinement category: NF = 2k+1
+// nodes covering the 8 children (child along an axis = node index >= k);
+// polynomial category: NF = k_f+1; identity: NF = NC, no sweeps.
+constexpr int TR_THREADS = 64;
+
+template <int KC, typename T>
+__device__ __forceinline__ void constraints_lds(T* X, uint32_t m, const T (&H)[2][(KC + 1) * (KC + 1)],
+                                                bool trans) {
+  constexpr int N = KC + 1, N2 = N * N;
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    const int s = mask_sub(m, d);
+    for (int line = threadIdx.x; line < N2; line += blockDim.x) {
+      const int p = line % N, q = line / N;
+      if (!hanging_line(m, d, p, q, KC)) continue;
+      T u[N];
+      const int stride = d == 0 ? 1 : d == 1 ? N : N2;
+      const int base = d == 0 ? p * N + q * N2 : d == 1 ? p + q * N2 : p + q * N;
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = X[base + r * stride];
+      if (trans) interp<N, T, true>(H, s, u);
+      else interp<N, T, false>(H, s, u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) X[base + r * stride] = u[r];
+    }
+  }
+  __syncthreads();
+}
+
+// out (NO along axis d) = P (NO x NI) applied along axis d of `in`; other
+// axes: sizes n_other0 (the lower axis) and n_other1
+template <int NI, int NO, typename T, bool TRANS>
+__device__ __forceinline__ void sweep_lds(const T* in, T* out, const T* __restrict__ P, int d, int na, int nb) {
+  // `in` has extent NI along d, `out` NO along d; the other two axes (in
+  // increasing order) have extents na, nb in both.  Layout x fastest.
+  const int lines = na * nb;
+  for (int line = threadIdx.x; line < lines; line += blockDim.x) {
+    const int p = line % na, q = line / na;
+    int sin, sout, bin, bout;
+    if (d == 0) { sin = 1; sout = 1; bin = (p + q * na) * NI; bout = (p + q * na) * NO; }
+    else if (d == 1) { sin = na; sout = na; bin = p + q * na * NI; bout = p + q * na * NO; }
+    else { sin = na * nb; sout = na * nb; bin = p + q * na; bout = p + q * na; }
+    T u[NI];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) u[r] = in[bin + r * sin];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc += (TRANS ? P[j * NO + i] : P[i * NI + j]) * u[j];
+      out[bout + i * sout] = acc;
+    }
+  }
+}
+
+// fine lattice node I (per axis) -> (child bit, local node)
+template <int KF, int NF>
+__device__ __forceinline__ void lattice_local(int I, int& child, int& a) {
+  if constexpr (NF == 2 * KF + 1) {
+    child = I >= KF ? 1 : 0;
+    a = I - child * KF;
+  } else {
+    child = 0;
+    a = I;
+  }
+}
+
+template <int KF, int KC, int NF, typename S, typename T>
+__global__ void __launch_bounds__(TR_THREADS)
+    prolongate_kernel(const int32_t* __restrict__ fent, int64_t nfc, const int32_t* __restrict__ cent,
+                      const uint32_t* __restrict__ cmask, int64_t ncc, const int32_t* __restrict__ group_coarse,
+                      const int32_t* __restrict__ group_fine, int64_t ngroups, int nchild,
+                      const uint8_t* __restrict__ valence, TrTab<T, NF, KC + 1> tab, const S* __restrict__ src,
+                      S* __restrict__ dst, int nv) {
+  constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
+  constexpr bool IDENT = (NF == NC) && (KF == KC);
+  __shared__ T X[NC3];
+  __shared__ T Y1[IDENT ? 1 : NF * NC * NC];
+  __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
+  __shared__ T Y3[IDENT ? 1 : NF3];
+  const int64_t g = blockIdx.x;
+  const int v = blockIdx.y;
+  const int64_t cc = group_coarse[g];
+  const uint32_t mc = cmask[cc];
+  for (int i = threadIdx.x; i < NC3; i += blockDim.x) {
+    const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
+    const int s = node_slot(a, b, c, KC);
+    const int32_t e = cent[s * ncc + cc];
+    X[i] = e < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v]);
+  }
+  if (mask_hanging(mc)) constraints_lds<KC, T>(X, mc, tab.H, false);
+  else __syncthreads();
+  const T* Y = X;
+  if constexpr (!IDENT) {
+    sweep_lds<NC, NF, T, false>(X, Y1, tab.P, 0, NC, NC);
+    __syncthreads();
+    sweep_lds<NC, NF, T, false>(Y1, Y2, tab.P, 1, NF, NC);
+    __syncthreads();
+    sweep_lds<NC, NF, T, false>(Y2, Y3, tab.P, 2, NF, NF);
+    __syncthreads();
+    Y = Y3;
+  }
+  for (int i = threadIdx.x; i < NF3; i += blockDim.x) {
+    const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
+    int cx, cy, cz, a, b, c;
+    lattice_local<KF, NF>(I, cx, a);
+    lattice_local<KF, NF>(J, cy, b);
+    lattice_local<KF, NF>(L, cz, c);
+    const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
+    const int64_t f = group_fine[child * ngroups + g];
+    const int s = node_slot(a, b, c, KF);
+    const int val = valence[s * nfc + f];
+    if (val == 0) continue;
+    const int32_t e = fent[s * nfc + f];
+    const int64_t idx = static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v;
+    add_to<S, T>(&dst[idx], Y[i] / static_cast<T>(val), val == 1);
+  }
+}
+
+template <int KF, int KC, int NF, typename S, typename T>
+__global__ void __launch_bounds__(TR_THREADS)
+    restrict_kernel(const int32_t* __restrict__ fent, int64_t nfc, const int32_t* __restrict__ cent,
+                    const uint32_t* __restrict__ cmask, int64_t ncc, const int32_t* __restrict__ group_coarse,
+                    const int32_t* __restrict__ group_fine, int64_t ngroups, int nchild,
+                    const uint8_t* __restrict__ valence, TrTab<T, NF, KC + 1> tab, const S* __restrict__ src,
+                    S* __restrict__ dst, int nv) {
+  constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
+  constexpr bool IDENT = (NF == NC) && (KF == KC);
+  __shared__ T X[NC3];
+  __shared__ T Y1[IDENT ? 1 : NF * NC * NC];
+  __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
+  __shared__ T Y3[IDENT ? 1 : NF3];
+  const int64_t g = blockIdx.x;
+  const int v = blockIdx.y;
+  const int64_t cc = group_coarse[g];
+  const uint32_t mc = cmask[cc];
+  T* Yw = IDENT ? X : Y3;
+  for (int i = threadIdx.x; i < NF3; i += blockDim.x) {
+    const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
+    int cx, cy, cz, a, b, c;
+    lattice_local<KF, NF>(I, cx, a);
+    lattice_local<KF, NF>(J, cy, b);
+    lattice_local<KF, NF>(L, cz, c);
+    const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
+    const int64_t f = group_fine[child * ngroups + g];
+    const int s = node_slot(a, b, c, KF);
+    const int val = valence[s * nfc + f];
+    T y = T(0);
+    if (val) {
+      const int32_t e = fent[s * nfc + f];
+      y = load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v]) / static_cast<T>(val);
+    }
+    Yw[i] = y;
+  }
+  __syncthreads();
+  if constexpr (!IDENT) {
+    sweep_lds<NF, NC, T, true>(Y3, Y2, tab.P, 2, NF, NF);
+    __syncthreads();
+    sweep_lds<NF, NC, T, true>(Y2, Y1, tab.P, 1, NF, NC);
+    __syncthreads();
+    sweep_lds<NF, NC, T, true>(Y1, X, tab.P, 0, NC, NC);
+    __syncthreads();
+  }
+  if (mask_hanging(mc)) constraints_lds<KC, T>(X, mc, tab.H, true);
+  for (int i = threadIdx.x; i < NC3; i += blockDim.x) {
+    const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
+    const int s = node_slot(a, b, c, KC);
+    const int32_t e = cent[s * ncc + cc];
+    if (e < 0) continue;
+    add_to<S, T>(&dst[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v], X[i], s == 26);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels
+constexpr int VEC_THREADS = 256;
+
+inline unsigned grid_for(int64_t n, int per_thread = 1) {
+  int64_t b = (n + static_cast<int64_t>(VEC_THREADS) * per_thread - 1) / (static_cast<int64_t>(VEC_THREADS) * per_thread);
+  if (b < 1) b = 1;
+  if (b > 1 << 20) b = 1 << 20;
+  return static_cast<unsigned>(b);
+}
+
+__global__ void fill_zero_kernel(uint32_t* __restrict__ x, int64_t nwords) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nwords;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    x[i] = 0u;
+}
+
+__global__ void fill_zero_bytes_kernel(uint8_t* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    x[i] = 0;
+}
+
+template <typename S>
+__global__ void cheb_kernel(int64_t n_dofs, int nv, int first, typename Acc<S>::type c_dd,
+                            typename Acc<S>::type c_r, const typename Acc<S>::type* __restrict__ t,
+                            const S* __restrict__ b, const typename Acc<S>::type* __restrict__ dinv,
+                            S* __restrict__ d, S* __restrict__ x) {
+  using A = typename Acc<S>::type;
+  const int64_t n = n_dofs * nv;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const A di = dinv[i / nv];
+    A dn;
+    if (first) {
+      dn = c_r * di * load_as<A>(b[i]);
+      x[i] = store_as<S>(dn);
+    } else {
+      dn = c_dd * load_as<A>(d[i]) + c_r * di * (load_as<A>(b[i]) - t[i]);
+      x[i] = store_as<S>(load_as<A>(x[i]) + dn);
+    }
+    d[i] = store_as<S>(dn);
+  }
+}
+
+template <typename S>
+__global__ void residual_kernel(int64_t n, const S* __restrict__ b, const typename Acc<S>::type* __restrict__ t,
+                                S* __restrict__ r) {
+  using A = typename Acc<S>::type;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    r[i] = store_as<S>(load_as<A>(b[i]) - t[i]);
+}
+
+template <typename S>
+__global__ void cast_from_f64_kernel(int64_t n, const double* __restrict__ src, S* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = store_as<S>(src[i]);
+}
+
+template <typename S>
+__global__ void cast_to_f64_kernel(int64_t n, const S* __restrict__ src, double* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = load_as<double>(src[i]);
+}
+
+template <typename A, typename B>
+__global__ void cast_kernel(int64_t n, const A* __restrict__ src, B* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = store_as<B>(load_as<float>(src[i]));
+}
+
+template <typename S>
+__global__ void acc_to_storage_kernel(int64_t n, const typename Acc<S>::type* __restrict__ src,
+                                      S* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = store_as<S>(src[i]);
+}
+
+template <typename A>
+__global__ void inverse_diag_kernel(int64_t n, const double* __restrict__ diag, A* __restrict__ dinv) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dinv[i] = diag[i] != 0.0 ? static_cast<A>(1.0 / diag[i]) : A(0);
+}
+
+// one wavefront per row: acc[row] = sum_j Ainv[row, j] b[j]
+template <typename S>
+__global__ void __launch_bounds__(256)
+    dense_matvec_kernel(int64_t n0, int nv, const typename Acc<S>::type* __restrict__ Ainv,
+                        const S* __restrict__ b, S* __restrict__ x) {
+  using A = typename Acc<S>::type;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x / 64) + threadIdx.x / 64;
+  const int v = blockIdx.y;
+  if (row >= n0) return;
+  A s = A(0);
+  for (int64_t j = lane; j < n0; j += 64) s += Ainv[row * n0 + j] * load_as<A>(b[j * nv + v]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[row * nv + v] = store_as<S>(s);
+}
+
+// ---- FP64 reductions and CG updates ----------------------------------------
+constexpr int DOT_BLOCKS = 512;
+
+__global__ void __launch_bounds__(256)
+    dot_stage1(int64_t n_dofs, int nv, const double* __restrict__ a, const double* __restrict__ b,
+               double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int v = blockIdx.y;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_dofs;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s += a[i * nv + v] * b[i * nv + v];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[v * DOT_BLOCKS + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) dot_stage2(int nv, const double* __restrict__ partial,
+                                                  double* __restrict__ result) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < DOT_BLOCKS; i += blockDim.x) s += partial[v * DOT_BLOCKS + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) result[v] = red[0];
+}
+
+__global__ void cg_xr_kernel(int64_t n_dofs, int nv, const double* __restrict__ num, const double* __restrict__ den,
+                             const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+                             double* __restrict__ r) {
+  const int64_t n = n_dofs * nv;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int v = static_cast<int>(i % nv);
+    const double alpha = den[v] != 0.0 ? num[v] / den[v] : 0.0;
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+__global__ void cg_p_kernel(int64_t n_dofs, int nv, const double* __restrict__ num, const double* __restrict__ sub,
+                            const double* __restrict__ den, const double* __restrict__ z, double* __restrict__ p) {
+  const int64_t n = n_dofs * nv;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int v = static_cast<int>(i % nv);
+    const double beta = den[v] != 0.0 ? (num[v] - (sub ? sub[v] : 0.0)) / den[v] : 0.0;
+    p[i] = z[i] + beta * p[i];
+  }
+}
+
+// ===========================================================================
+// host launchers
+namespace {
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(MFMG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return;
+  if (bytes % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 4 == 0) {
+    fill_zero_kernel<<<grid_for(bytes / 4, 4), VEC_THREADS, 0, s>>>(static_cast<uint32_t*>(p), bytes / 4);
+  } else {
+    fill_zero_bytes_kernel<<<grid_for(bytes, 4), VEC_THREADS, 0, s>>>(static_cast<uint8_t*>(p), bytes);
+  }
+  check_launch();
+}
+
+template <int K, typename S>
+void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t s) {
+  using T = typename Acc<S>::type;
+  constexpr int N = K + 1, CPB = CPBOf<N>::v;
+  zero_bytes(dst, c.n_shared * nv * static_cast<int64_t>(sizeof(T)), s);
+  if (c.n_cells == 0) return;
+  static const OpTab<T, N> tab = make_optab<T, N>();
+  dim3 grid(static_cast<unsigned>((c.n_cells + CPB - 1) / CPB), nv);
+  vmult_kernel<K, S, T><<<grid, CPB * N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab,
+                                                    static_cast<const S*>(src), static_cast<T*>(dst), nv);
+  check_launch();
+}
+
+template <typename S>
+void vmult_s(const CellView& c, int nv, void* dst, const void* src, hipStream_t s) {
+  switch (c.k) {
+    case 1: vmult_k<1, S>(c, nv, dst, src, s); break;
+    case 2: vmult_k<2, S>(c, nv, dst, src, s); break;
+    case 3: vmult_k<3, S>(c, nv, dst, src, s); break;
+    case 4: vmult_k<4, S>(c, nv, dst, src, s); break;
+    case 5: vmult_k<5, S>(c, nv, dst, src, s); break;
+    case 6: vmult_k<6, S>(c, nv, dst, src, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
+  }
+}
+
+template <int K>
+void diag_k(const CellView& c, double* diag, hipStream_t s) {
+  constexpr int N = K + 1;
+  zero_bytes(diag, c.n_shared * 8, s);
+  if (c.n_cells == 0) return;
+  static const OpTab<double, N> tab = make_optab<double, N>();
+  diag_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab, diag);
+  check_launch();
+}
+
+template <int K>
+void rhs_k(const CellView& c, int kind, const double* params, int n_terms, int nv, double* b, hipStream_t s) {
+  constexpr int N = K + 1;
+  zero_bytes(b, c.n_shared * nv * 8, s);
+  if (c.n_cells == 0) return;
+  static const OpTab<double, N> tab = make_optab<double, N>();
+  static const Gauss1D<N> g = make_gauss<N>();
+  dim3 grid(static_cast<unsigned>(c.n_cells), nv);
+  rhs_kernel<K><<<grid, N * N, 0, s>>>(c.ent, c.mask, c.ijk, c.n_cells, c.h0, c.lo, tab, g, kind, params,
+                                       n_terms, b, nv);
+  check_launch();
+}
+
+template <typename T, int NF, int NC>
+TrTab<T, NF, NC> make_trtab(int kf, int kc) {
+  TrTab<T, NF, NC> t;
+  const Tables1D& tc = tables(kc);
+  for (int i = 0; i < NC * NC; ++i) {
+    t.H[0][i] = static_cast<T>(tc.H[0][i]);
+    t.H[1][i] = static_cast<T>(tc.H[1][i]);
+  }
+  if (kf == kc && NF == 2 * kc + 1) {
+    for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>(tc.T[i]);
+  } else if (kf != kc) {
+    std::vector<double> P = p_transfer_matrix(kf, kc);
+    for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>(P[i]);
+  } else {
+    for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>((i / NC) == (i % NC) ? 1.0 : 0.0);
+  }
+  return t;
+}
+
+template <int KF, int KC, int NF, typename S>
+void transfer_launch(bool prolong, const CellView& f, const CellView& c, const TransferView& t,
+                     const int32_t* gc, const int32_t* gf, int64_t ng, int nchild, int nv, void* dst,
+                     const void* src, hipStream_t s) {
+  using T = typename Acc<S>::type;
+  if (ng == 0) return;
+  static const TrTab<T, NF, KC + 1> tab = make_trtab<T, NF, KC + 1>(KF, KC);
+  dim3 grid(static_cast<unsigned>(ng), nv);
+  if (prolong)
+    prolongate_kernel<KF, KC, NF, S, T><<<grid, TR_THREADS, 0, s>>>(
+        f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc, gf, ng, nchild, t.valence, tab,
+        static_cast<const S*>(src), static_cast<S*>(dst), nv);
+  else
+    restrict_kernel<KF, KC, NF, S, T><<<grid, TR_THREADS, 0, s>>>(
+        f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc, gf, ng, nchild, t.valence, tab,
+        static_cast<const S*>(src), static_cast<S*>(dst), nv);
+  check_launch();
+}
+
+template <int K, typename S>
+void transfer_h(bool prolong, const CellView& f, const CellView& c, const TransferView& t, int nv, void* dst,
+                const void* src, hipStream_t s) {
+  transfer_launch<K, K, K + 1, S>(prolong, f, c, t, t.ident_coarse, t.ident_fine, t.n_ident, 1, nv, dst, src, s);
+  transfer_launch<K, K, 2 * K + 1, S>(prolong, f, c, t, t.refined_coarse, t.refined_fine, t.n_refined, 8, nv,
+                                     dst, src, s);
+}
+
+template <typename S>
+void transfer_s(bool prolong, const CellView& f, const CellView& c, const TransferView& t, int nv, void* dst,
+                const void* src, hipStream_t s) {
+  if (!t.polynomial) {
+    MFMG_REQUIRE(f.k == c.k, MFMG_ERR_INVALID_ARG, "geometric transfer needs equal degrees");
+    switch (f.k) {
+      case 1: transfer_h<1, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 2: transfer_h<2, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 3: transfer_h<3, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 4: transfer_h<4, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 5: transfer_h<5, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 6: transfer_h<6, S>(prolong, f, c, t, nv, dst, src, s); break;
+      default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
+    }
+    return;
+  }
+  const int key = f.k * 10 + c.k;
+  switch (key) {
+#define MFMG_P(KF, KC)                                                                                  \
+  case KF * 10 + KC:                                                                                   \
+    transfer_launch<KF, KC, KF + 1, S>(prolong, f, c, t, t.ident_coarse, t.ident_fine, t.n_ident, 1, nv, dst, \
+                                       src, s);                                                        \
+    break;
+    MFMG_P(2, 1)
+    MFMG_P(3, 1)
+    MFMG_P(4, 2)
+    MFMG_P(5, 2)
+    MFMG_P(6, 3)
+#undef MFMG_P
+    default:
+      throw Error(MFMG_ERR_UNSUPPORTED, "polynomial transfer pair");
+  }
+}
+
+}  // namespace
+
+void launch_vmult(const CellView& c, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
+  switch (dtype) {
+    case MFMG_F64: vmult_s<double>(c, nv, dst, src, s); break;
+    case MFMG_F32: vmult_s<float>(c, nv, dst, src, s); break;
+    case MFMG_BF16: vmult_s<bf16>(c, nv, dst, src, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+}
+
+void launch_diagonal(const CellView& c, double* diag, hipStream_t s) {
+  switch (c.k) {
+    case 1: diag_k<1>(c, diag, s); break;
+    case 2: diag_k<2>(c, diag, s); break;
+    case 3: diag_k<3>(c, diag, s); break;
+    case 4: diag_k<4>(c, diag, s); break;
+    case 5: diag_k<5>(c, diag, s); break;
+    case 6: diag_k<6>(c, diag, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
+  }
+}
+
+void launch_rhs(const CellView& c, int kind, const double* params, int n_terms, int nv, double* b,
+                hipStream_t s) {
+  switch (c.k) {
+    case 1: rhs_k<1>(c, kind, params, n_terms, nv, b, s); break;
+    case 2: rhs_k<2>(c, kind, params, n_terms, nv, b, s); break;
+    case 3: rhs_k<3>(c, kind, params, n_terms, nv, b, s); break;
+    case 4: rhs_k<4>(c, kind, params, n_terms, nv, b, s); break;
+    case 5: rhs_k<5>(c, kind, params, n_terms, nv, b, s); break;
+    case 6: rhs_k<6>(c, kind, params, n_terms, nv, b, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
+  }
+}
+
+void launch_prolongate(const CellView& f, const CellView& c, const TransferView& t, int dtype, int nv, void* dst,
+                       const void* src, hipStream_t s) {
+  switch (dtype) {
+    case MFMG_F64: transfer_s<double>(true, f, c, t, nv, dst, src, s); break;
+    case MFMG_F32: transfer_s<float>(true, f, c, t, nv, dst, src, s); break;
+    case MFMG_BF16: transfer_s<bf16>(true, f, c, t, nv, dst, src, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+}
+
+void launch_restrict(const CellView& f, const CellView& c, const TransferView& t, int dtype, int nv, void* dst,
+                     const void* src, hipStream_t s) {
+  switch (dtype) {
+    case MFMG_F64: transfer_s<double>(false, f, c, t, nv, dst, src, s); break;
+    case MFMG_F32: transfer_s<float>(false, f, c, t, nv, dst, src, s); break;
+    case MFMG_BF16: transfer_s<bf16>(false, f, c, t, nv, dst, src, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+}
+
+void launch_fill(int, void* x, int64_t n_bytes, hipStream_t s) { zero_bytes(x, n_bytes, s); }
+
+void launch_cheb_step(int dtype, int64_t n_dofs, int nv, bool first, double c_dd, double c_r, const void* t,
+                      const void* b, const void* dinv, void* d, void* x, hipStream_t s) {
+  const unsigned g = grid_for(n_dofs * nv);
+  switch (dtype) {
+    case MFMG_F64:
+      cheb_kernel<double><<<g, VEC_THREADS, 0, s>>>(n_dofs, nv, first, c_dd, c_r, static_cast<const double*>(t),
+                                                    static_cast<const double*>(b), static_cast<const double*>(dinv),
+                                                    static_cast<double*>(d), static_cast<double*>(x));
+      break;
+    case MFMG_F32:
+      cheb_kernel<float><<<g, VEC_THREADS, 0, s>>>(n_dofs, nv, first, static_cast<float>(c_dd),
+                                                   static_cast<float>(c_r), static_cast<const float*>(t),
+                                                   static_cast<const float*>(b), static_cast<const float*>(dinv),
+                                                   static_cast<float*>(d), static_cast<float*>(x));
+      break;
+    case MFMG_BF16:
+      cheb_kernel<bf16><<<g, VEC_THREADS, 0, s>>>(n_dofs, nv, first, static_cast<float>(c_dd),
+                                                  static_cast<float>(c_r), static_cast<const float*>(t),
+                                                  static_cast<const bf16*>(b), static_cast<const float*>(dinv),
+                                                  static_cast<bf16*>(d), static_cast<bf16*>(x));
+      break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_residual_update(int dtype, int64_t n, const void* b, const void* t, void* r, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  switch (dtype) {
+    case MFMG_F64:
+      residual_kernel<double><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const double*>(b),
+                                                        static_cast<const double*>(t), static_cast<double*>(r));
+      break;
+    case MFMG_F32:
+      residual_kernel<float><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const float*>(b),
+                                                       static_cast<const float*>(t), static_cast<float*>(r));
+      break;
+    case MFMG_BF16:
+      residual_kernel<bf16><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const bf16*>(b), static_cast<const float*>(t),
+                                                      static_cast<bf16*>(r));
+      break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_cast_from_f64(int dtype, int64_t n, const double* src, void* dst, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  switch (dtype) {
+    case MFMG_F64: cast_from_f64_kernel<double><<<g, VEC_THREADS, 0, s>>>(n, src, static_cast<double*>(dst)); break;
+    case MFMG_F32: cast_from_f64_kernel<float><<<g, VEC_THREADS, 0, s>>>(n, src, static_cast<float*>(dst)); break;
+    case MFMG_BF16: cast_from_f64_kernel<bf16><<<g, VEC_THREADS, 0, s>>>(n, src, static_cast<bf16*>(dst)); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_cast_to_f64(int dtype, int64_t n, const void* src, double* dst, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  switch (dtype) {
+    case MFMG_F64: cast_to_f64_kernel<double><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const double*>(src), dst); break;
+    case MFMG_F32: cast_to_f64_kernel<float><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const float*>(src), dst); break;
+    case MFMG_BF16: cast_to_f64_kernel<bf16><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const bf16*>(src), dst); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_cast(int dtype_src, int dtype_dst, int64_t n, const void* src, void* dst, hipStream_t s) {
+  if (dtype_src == MFMG_F64) { launch_cast_from_f64(dtype_dst, n, static_cast<const double*>(src), dst, s); return; }
+  if (dtype_dst == MFMG_F64) { launch_cast_to_f64(dtype_src, n, src, static_cast<double*>(dst), s); return; }
+  const unsigned g = grid_for(n);
+  if (dtype_src == MFMG_F32 && dtype_dst == MFMG_BF16)
+    cast_kernel<float, bf16><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const float*>(src), static_cast<bf16*>(dst));
+  else if (dtype_src == MFMG_BF16 && dtype_dst == MFMG_F32)
+    cast_kernel<bf16, float><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const bf16*>(src), static_cast<float*>(dst));
+  else if (dtype_src == dtype_dst)
+    (void)hipMemcpyAsync(dst, src, n * dtype_size(dtype_src), hipMemcpyDeviceToDevice, s);
+  else
+    throw Error(MFMG_ERR_UNSUPPORTED, "cast");
+  check_launch();
+}
+
+void launch_acc_to_storage(int dtype, int64_t n, const void* acc, void* dst, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  switch (dtype) {
+    case MFMG_F64:
+      acc_to_storage_kernel<double><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const double*>(acc),
+                                                              static_cast<double*>(dst));
+      break;
+    case MFMG_F32:
+      acc_to_storage_kernel<float><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const float*>(acc),
+                                                             static_cast<float*>(dst));
+      break;
+    case MFMG_BF16:
+      acc_to_storage_kernel<bf16><<<g, VEC_THREADS, 0, s>>>(n, static_cast<const float*>(acc),
+                                                            static_cast<bf16*>(dst));
+      break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_inverse_diag(int dtype, int64_t n, const double* diag, void* dinv, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  if (dtype == MFMG_F64)
+    inverse_diag_kernel<double><<<g, VEC_THREADS, 0, s>>>(n, diag, static_cast<double*>(dinv));
+  else
+    inverse_diag_kernel<float><<<g, VEC_THREADS, 0, s>>>(n, diag, static_cast<float*>(dinv));
+  check_launch();
+}
+
+void launch_dense_matvec(int dtype, int64_t n0, int nv, const void* Ainv, const void* b, void* x, void*,
+                         hipStream_t s) {
+  if (n0 == 0) return;
+  dim3 grid(static_cast<unsigned>((n0 + 3) / 4), nv);
+  switch (dtype) {
+    case MFMG_F64:
+      dense_matvec_kernel<double><<<grid, 256, 0, s>>>(n0, nv, static_cast<const double*>(Ainv),
+                                                       static_cast<const double*>(b), static_cast<double*>(x));
+      break;
+    case MFMG_F32:
+      dense_matvec_kernel<float><<<grid, 256, 0, s>>>(n0, nv, static_cast<const float*>(Ainv),
+                                                      static_cast<const float*>(b), static_cast<float*>(x));
+      break;
+    case MFMG_BF16:
+      dense_matvec_kernel<bf16><<<grid, 256, 0, s>>>(n0, nv, static_cast<const float*>(Ainv),
+                                                     static_cast<const bf16*>(b), static_cast<bf16*>(x));
+      break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+int dot_partials_needed() { return DOT_BLOCKS; }
+
+void launch_dot(int64_t n_dofs, int nv, const double* a, const double* b, double* partial, double* result,
+                hipStream_t s) {
+  dot_stage1<<<dim3(DOT_BLOCKS, nv), 256, 0, s>>>(n_dofs, nv, a, b, partial);
+  check_launch();
+  dot_stage2<<<nv, 256, 0, s>>>(nv, partial, result);
+  check_launch();
+}
+
+void launch_cg_update_xr(int64_t n_dofs, int nv, const double* num, const double* den, const double* p,
+                         const double* q, double* x, double* r, hipStream_t s) {
+  cg_xr_kernel<<<grid_for(n_dofs * nv), VEC_THREADS, 0, s>>>(n_dofs, nv, num, den, p, q, x, r);
+  check_launch();
+}
+
+void launch_cg_update_p(int64_t n_dofs, int nv, const double* num, const double* sub, const double* den,
+                        const double* z, double* p, hipStream_t s) {
+  cg_p_kernel<<<grid_for(n_dofs * nv), VEC_THREADS, 0, s>>>(n_dofs, nv, num, sub, den, z, p);
+  check_launch();
+}
+
+}  // namespace mfmg

@@ -1,0 +1,84 @@
+// Host-callable launchers of the device kernels (one HIP translation unit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfmg {
+
+// Per-level device view of the cell data.
+struct CellView {
+  const int32_t* ent = nullptr;  // [27][n_cells]
+  const uint32_t* mask = nullptr;
+  const int32_t* ijk = nullptr;  // [n_cells][3] cell coordinates on its level
+  int64_t n_cells = 0;
+  int64_t n_dofs = 0;
+  int64_t n_shared = 0;
+  int k = 1;
+  double h0 = 1.0;  // coarse-grid cell size
+  double lo = 0.0;  // domain lower corner
+};
+
+struct TransferView {
+  bool polynomial = false;
+  const int32_t* ident_coarse = nullptr;
+  const int32_t* ident_fine = nullptr;
+  int64_t n_ident = 0;
+  const int32_t* refined_coarse = nullptr;
+  const int32_t* refined_fine = nullptr;  // [8][n_refined]
+  int64_t n_refined = 0;
+  const uint8_t* valence = nullptr;       // [27][n_fine_cells]
+};
+
+// dtype: MFMG_F64 / MFMG_F32 / MFMG_BF16 for the vectors named "S"; the
+// "acc" vectors are double for F64 and float otherwise.
+
+// dst_acc = A src  (dst zeroed here on the shared range, interiors overwritten)
+void launch_vmult(const CellView& c, int dtype, int nv, void* dst_acc, const void* src, hipStream_t s);
+// diag (FP64) = diagonal of A
+void launch_diagonal(const CellView& c, double* diag, hipStream_t s);
+// b (FP64) += load vector; kind 0 const, 1 gaussians (params on device, n_terms per vector)
+void launch_rhs(const CellView& c, int kind, const double* dparams, int n_terms, int nv, double* b,
+                hipStream_t s);
+// dst_fine (S) += P src_coarse (S)
+void launch_prolongate(const CellView& fine, const CellView& coarse, const TransferView& t, int dtype, int nv,
+                       void* dst_fine, const void* src_coarse, hipStream_t s);
+// dst_coarse (S) += P^T src_fine (S)
+void launch_restrict(const CellView& fine, const CellView& coarse, const TransferView& t, int dtype, int nv,
+                     void* dst_coarse, const void* src_fine, hipStream_t s);
+
+// ---- vector kernels (n = number of entries, i.e. n_dofs * nv) --------------
+void launch_fill(int dtype_bytes, void* x, int64_t n_bytes, hipStream_t s);
+// Chebyshev step: first (x = 0): d = dinv*b/theta, x = d;
+// else d = c_dd*d + c_r*dinv*(b - t), x += d.   t, dinv: acc type.
+void launch_cheb_step(int dtype, int64_t n_dofs, int nv, bool first, double c_dd, double c_r,
+                      const void* t, const void* b, const void* dinv, void* d, void* x, hipStream_t s);
+// r = b - t (r, b: S; t: acc)
+void launch_residual_update(int dtype, int64_t n, const void* b, const void* t, void* r, hipStream_t s);
+// cast between FP64 and S
+void launch_cast_from_f64(int dtype, int64_t n, const double* src, void* dst, hipStream_t s);
+void launch_cast_to_f64(int dtype, int64_t n, const void* src, double* dst, hipStream_t s);
+// dst (dtype_dst) = src (dtype_src)
+void launch_cast(int dtype_src, int dtype_dst, int64_t n, const void* src, void* dst, hipStream_t s);
+// acc -> S
+void launch_acc_to_storage(int dtype, int64_t n, const void* acc, void* dst, hipStream_t s);
+// dinv = 1/diag in acc type (0 where diag == 0)
+void launch_inverse_diag(int dtype, int64_t n, const double* diag, void* dinv, hipStream_t s);
+// x (S) = Ainv (acc type, n0 x n0 row-major) b (S); nv interleaved vectors
+void launch_dense_matvec(int dtype, int64_t n0, int nv, const void* Ainv, const void* b, void* x,
+                         void* acc_tmp, hipStream_t s);
+
+// ---- FP64 CG helpers --------------------------------------------------------
+// partial[blk*nv+v] = sum_i a[i*nv+v]*b[i*nv+v]; result[v] via second stage.
+void launch_dot(int64_t n_dofs, int nv, const double* a, const double* b, double* partial, double* result,
+                hipStream_t s);
+int dot_partials_needed();
+// x += alpha[v] p; r -= alpha[v] q   with alpha = num[v]/den[v]
+void launch_cg_update_xr(int64_t n_dofs, int nv, const double* num, const double* den, const double* p,
+                         const double* q, double* x, double* r, hipStream_t s);
+// p = z + beta[v] p  with beta = (num[v] - sub[v]) / den[v] (sub may be null)
+void launch_cg_update_p(int64_t n_dofs, int nv, const double* num, const double* sub, const double* den,
+                        const double* z, double* p, hipStream_t s);
+
+}  // namespace mfmg

@@ -1,0 +1,91 @@
+// Geometry of the 27 entity slots of a hexahedron and the hanging-node line
+// rule, shared by host set-up and device kernels.
+//
+// Slots: 0-7 vertices (a + 2b + 4c), 8-11 edges along x (8 + b + 2c),
+// 12-15 edges along y (12 + a + 2c), 16-19 edges along z (16 + a + 2b),
+// 20-21 faces normal to x (20 + a), 22-23 normal to y (22 + b), 24-25 normal
+// to z (24 + c), 26 interior; a, b, c in {0, 1} select the low/high side.
+//
+// Within an entity, DoFs are ordered over the entity's interior node indices
+// with x fastest, then y, then z.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfmg {
+
+// side of slot s along axis d: 0 / 1 (at node 0 / node k), -1 (extends)
+__host__ __device__ constexpr int slot_side(int s, int d) {
+  return s < 8 ? ((s >> d) & 1)
+         : s < 12 ? (d == 0 ? -1 : d == 1 ? ((s - 8) & 1) : (((s - 8) >> 1) & 1))
+         : s < 16 ? (d == 1 ? -1 : d == 0 ? ((s - 12) & 1) : (((s - 12) >> 1) & 1))
+         : s < 20 ? (d == 2 ? -1 : d == 0 ? ((s - 16) & 1) : (((s - 16) >> 1) & 1))
+         : s < 22 ? (d == 0 ? (s - 20) : -1)
+         : s < 24 ? (d == 1 ? (s - 22) : -1)
+         : s < 26 ? (d == 2 ? (s - 24) : -1)
+                  : -1;
+}
+
+// slot of node (a, b, c), 0 <= a, b, c <= k
+__host__ __device__ constexpr int node_slot(int a, int b, int c, int k) {
+  int sa = a == 0 ? 0 : a == k ? 1 : -1;
+  int sb = b == 0 ? 0 : b == k ? 1 : -1;
+  int sc = c == 0 ? 0 : c == k ? 1 : -1;
+  int ext = (sa < 0) + (sb < 0) + (sc < 0);
+  if (ext == 0) return sa + 2 * sb + 4 * sc;
+  if (ext == 1) return sa < 0 ? 8 + sb + 2 * sc : sb < 0 ? 12 + sa + 2 * sc : 16 + sa + 2 * sb;
+  if (ext == 2) return sa >= 0 ? 20 + sa : sb >= 0 ? 22 + sb : 24 + sc;
+  return 26;
+}
+
+// offset of node (a, b, c) inside its slot's entity
+__host__ __device__ constexpr int node_offset(int a, int b, int c, int k) {
+  int km = k - 1;
+  int ea = (a != 0 && a != k), eb = (b != 0 && b != k), ec = (c != 0 && c != k);
+  int off = 0, stride = 1;
+  if (ea) { off += (a - 1) * stride; stride *= km; }
+  if (eb) { off += (b - 1) * stride; stride *= km; }
+  if (ec) { off += (c - 1) * stride; }
+  return off;
+}
+
+__host__ __device__ constexpr int slot_size(int s, int k) {
+  int km = k - 1;
+  return s < 8 ? 1 : s < 20 ? km : s < 26 ? km * km : km * km * km;
+}
+
+// Mask bits.
+__host__ __device__ inline int mask_sub(uint32_t m, int d) { return (m >> d) & 1; }
+__host__ __device__ inline int mask_face(uint32_t m, int d) { return (m >> (3 + d)) & 1; }
+__host__ __device__ inline int mask_edge(uint32_t m, int d) { return (m >> (6 + d)) & 1; }
+__host__ __device__ inline int mask_level(uint32_t m) { return (m >> 16) & 0xff; }
+__host__ __device__ inline bool mask_hanging(uint32_t m) { return (m & 0x1f8u) != 0; }
+
+// Is the line along axis d through local node indices (p, q) of the other two
+// axes (in increasing axis order) interpolated by the hanging-node rule?
+// Lines of a hanging face normal to e (e != d) at the face's node index, and
+// the hanging edge along d itself.
+__host__ __device__ inline bool hanging_line(uint32_t m, int d, int p, int q, int k) {
+  const int e = d == 0 ? 1 : 0;
+  const int f = d == 2 ? 1 : 2;
+  const bool pe = p == mask_sub(m, e) * k;
+  const bool qf = q == mask_sub(m, f) * k;
+  return (mask_face(m, e) && pe) || (mask_face(m, f) && qf) || (mask_edge(m, d) && pe && qf);
+}
+
+// Is slot s constrained (its entity replaced by the parent's entity)?
+__host__ __device__ inline bool slot_hanging(uint32_t m, int s) {
+  for (int d = 0; d < 3; ++d)
+    if (mask_face(m, d) && slot_side(s, d) == mask_sub(m, d)) return true;
+  for (int d = 0; d < 3; ++d) {
+    const int e = d == 0 ? 1 : 0;
+    const int f = d == 2 ? 1 : 2;
+    if (mask_edge(m, d) && slot_side(s, e) == mask_sub(m, e) && slot_side(s, f) == mask_sub(m, f))
+      return true;
+  }
+  return false;
+}
+
+}  // namespace mfmg

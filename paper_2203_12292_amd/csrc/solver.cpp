@@ -1,0 +1,476 @@
+// Level set-up and the multigrid algorithms on top of the kernels:
+// Chebyshev-Jacobi smoothing (Section 3.3), the V-cycle (Algorithms 1-2,
+// global-coarsening branch), the exact coarse solver and PCG (Section 2).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <thread>
+
+#include "context.hpp"
+#include "fe1d.hpp"
+
+namespace mfmg {
+
+namespace {
+
+int acc_dtype(int dtype) { return dtype == MFMG_F64 ? MFMG_F64 : MFMG_F32; }
+
+void sync(hipStream_t s) { MFMG_HIP(hipStreamSynchronize(s)); }
+
+// Largest eigenvalue of a small symmetric matrix (cyclic Jacobi rotations).
+double max_eig_sym(std::vector<double> A, int n) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < n; ++r) {
+          double arp = A[r * n + p], arq = A[r * n + q];
+          A[r * n + p] = c * arp - s * arq;
+          A[r * n + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < n; ++r) {
+          double apr = A[p * n + r], aqr = A[q * n + r];
+          A[p * n + r] = c * apr - s * aqr;
+          A[q * n + r] = s * apr + c * aqr;
+        }
+      }
+  }
+  double m = -1e300;
+  for (int i = 0; i < n; ++i) m = std::max(m, A[i * n + i]);
+  return m;
+}
+
+// Dense inverse of an SPD matrix: Cholesky A = L L^T, then columns of A^{-1}
+// by forward/backward substitution (columns in parallel threads).
+std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
+  for (int64_t j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int64_t q = 0; q < j; ++q) d -= A[j * n + q] * A[j * n + q];
+    MFMG_REQUIRE(d > 0.0, MFMG_ERR_BREAKDOWN, "coarse matrix is not positive definite");
+    d = std::sqrt(d);
+    A[j * n + j] = d;
+    const double inv = 1.0 / d;
+    const int64_t rows = n - j - 1;
+    auto work = [&](int64_t r0, int64_t r1) {
+      for (int64_t i = r0; i < r1; ++i) {
+        double s = A[i * n + j];
+        const double* ai = &A[i * n];
+        const double* aj = &A[j * n];
+        for (int64_t q = 0; q < j; ++q) s -= ai[q] * aj[q];
+        A[i * n + j] = s * inv;
+      }
+    };
+    if (rows > 256) {
+      unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (unsigned t = 0; t < nt; ++t) {
+        int64_t r0 = j + 1 + rows * t / nt, r1 = j + 1 + rows * (t + 1) / nt;
+        th.emplace_back(work, r0, r1);
+      }
+      for (auto& x : th) x.join();
+    } else {
+      work(j + 1, n);
+    }
+  }
+  std::vector<double> inv(static_cast<size_t>(n * n), 0.0);
+  auto cols = [&](int64_t c0, int64_t c1) {
+    std::vector<double> y(n);
+    for (int64_t c = c0; c < c1; ++c) {
+      for (int64_t i = 0; i < n; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int64_t q = 0; q < i; ++q) s -= A[i * n + q] * y[q];
+        y[i] = s / A[i * n + i];
+      }
+      for (int64_t i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int64_t q = i + 1; q < n; ++q) s -= A[q * n + i] * inv[q * n + c];
+        inv[i * n + c] = s / A[i * n + i];
+      }
+    }
+  };
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 256) nt = 1;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) th.emplace_back(cols, n * t / nt, n * (t + 1) / nt);
+  for (auto& x : th) x.join();
+  return inv;
+}
+
+std::vector<std::pair<int, int>> level_pairs(int n_meshes, int k, int scheme) {
+  // (mesh index, degree), coarse to fine; mesh index 0 = coarse grid
+  std::vector<int> degs{k};
+  while (degs.back() > 1) degs.push_back(degs.back() / 2);  // fine to coarse
+  std::vector<std::pair<int, int>> p;                       // fine to coarse
+  const int fine = n_meshes - 1;
+  if (scheme == MFMG_SCHEME_H) {
+    for (int m = fine; m >= 0; --m) p.push_back({m, k});
+  } else if (scheme == MFMG_SCHEME_P_THEN_H) {
+    for (int d : degs) p.push_back({fine, d});
+    for (int m = fine - 1; m >= 0; --m) p.push_back({m, 1});
+  } else if (scheme == MFMG_SCHEME_H_THEN_P) {
+    for (int m = fine; m >= 0; --m) p.push_back({m, k});
+    for (size_t i = 1; i < degs.size(); ++i) p.push_back({0, degs[i]});
+  } else {
+    throw Error(MFMG_ERR_INVALID_ARG, "unknown level scheme");
+  }
+  std::reverse(p.begin(), p.end());
+  return p;
+}
+
+void estimate_eigenvalues(Context& ctx, Level& L, int iters, double safety, double range, hipStream_t s) {
+  const int64_t n = L.n_dofs;
+  if (n == 0) { L.lmin = 1.0 / range; L.lmax = 1.0; return; }
+  DeviceArray<double> x(n), r(n), z(n), p(n), q(n), part(dot_partials_needed()), sc(4);
+  std::vector<double> ones(n, 1.0);
+  MFMG_HIP(hipMemcpy(r.ptr, ones.data(), n * 8, hipMemcpyHostToDevice));
+  const double* dinv = reinterpret_cast<const double*>(L.dinv.ptr);
+  std::vector<double> hd(n);
+  // z = D^{-1} r on the host-visible path: reuse the Chebyshev kernel with b=r
+  auto precond = [&](double* dst, const double* src) {
+    launch_cheb_step(MFMG_F64, n, 1, true, 0.0, 1.0, nullptr, src, dinv, dst, x.ptr, s);
+  };
+  precond(z.ptr, r.ptr);
+  MFMG_HIP(hipMemcpyAsync(p.ptr, z.ptr, n * 8, hipMemcpyDeviceToDevice, s));
+  launch_dot(n, 1, r.ptr, z.ptr, part.ptr, sc.ptr + 0, s);  // rz
+  double rz;
+  MFMG_HIP(hipMemcpyAsync(&rz, sc.ptr, 8, hipMemcpyDeviceToHost, s));
+  sync(s);
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < std::min<int64_t>(iters, n); ++it) {
+    launch_vmult(L.view, MFMG_F64, 1, q.ptr, p.ptr, s);
+    launch_dot(n, 1, p.ptr, q.ptr, part.ptr, sc.ptr + 1, s);  // pAp
+    double pap;
+    MFMG_HIP(hipMemcpyAsync(&pap, sc.ptr + 1, 8, hipMemcpyDeviceToHost, s));
+    sync(s);
+    if (!(pap > 0.0) || !(rz > 0.0)) break;
+    // r -= alpha q (x unused)
+    launch_cg_update_xr(n, 1, sc.ptr + 0, sc.ptr + 1, p.ptr, q.ptr, x.ptr, r.ptr, s);
+    precond(z.ptr, r.ptr);
+    launch_dot(n, 1, r.ptr, z.ptr, part.ptr, sc.ptr + 2, s);  // rz_new
+    double rzn;
+    MFMG_HIP(hipMemcpyAsync(&rzn, sc.ptr + 2, 8, hipMemcpyDeviceToHost, s));
+    sync(s);
+    const double alpha = rz / pap, beta = rzn / rz;
+    alphas.push_back(alpha);
+    betas.push_back(beta);
+    if (!(rzn > 0.0)) break;
+    launch_cg_update_p(n, 1, sc.ptr + 2, nullptr, sc.ptr + 0, z.ptr, p.ptr, s);
+    MFMG_HIP(hipMemcpyAsync(sc.ptr, sc.ptr + 2, 8, hipMemcpyDeviceToDevice, s));
+    rz = rzn;
+  }
+  const int m = static_cast<int>(alphas.size());
+  double lam = 1.0;
+  if (m > 0) {
+    std::vector<double> T(m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+      T[j * m + j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
+      if (j + 1 < m) T[j * m + j + 1] = T[(j + 1) * m + j] = std::sqrt(betas[j]) / alphas[j];
+    }
+    lam = max_eig_sym(T, m);
+  }
+  L.lmax = safety * lam;
+  L.lmin = L.lmax / range;
+}
+
+template <typename T>
+void upload_into(DeviceArray<T>& d, const std::vector<T>& h) { d.upload(h); }
+
+}  // namespace
+
+void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc& desc, hipStream_t s) {
+  MFMG_REQUIRE(desc.degree >= 1 && desc.degree <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
+  ctx.desc = desc;
+  ctx.stream = s;
+  ctx.meshes = mesh.gc;
+  ctx.max_rhs = desc.max_rhs > 0 ? desc.max_rhs : 1;
+  MFMG_REQUIRE(ctx.max_rhs <= 8, MFMG_ERR_UNSUPPORTED, "max_rhs must be <= 8");
+  ctx.cheb_degree = desc.cheb_degree > 0 ? desc.cheb_degree : 3;
+  const double range = desc.smoothing_range > 0 ? desc.smoothing_range : 20.0;
+  const double safety = desc.eig_safety > 0 ? desc.eig_safety : 1.2;
+  const int eig_it = desc.eig_iterations > 0 ? desc.eig_iterations : 15;
+  const auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);
+  MFMG_REQUIRE(pairs.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
+  const int nl = static_cast<int>(pairs.size());
+  ctx.levels.clear();
+  ctx.levels.resize(nl);
+  std::vector<LevelDofs> host(nl);
+  for (int l = 0; l < nl; ++l) {
+    Level& L = ctx.levels[l];
+    L.mesh = pairs[l].first;
+    L.k = pairs[l].second;
+    if (desc.n_level_dtype <= 0) L.dtype = MFMG_F64;
+    else L.dtype = desc.level_dtype[std::min(l, desc.n_level_dtype - 1)];
+    MFMG_REQUIRE(L.dtype >= MFMG_F64 && L.dtype <= MFMG_BF16, MFMG_ERR_UNSUPPORTED, "level dtype");
+    host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0);
+    const LevelDofs& H = host[l];
+    L.n_dofs = H.n_dofs;
+    L.n_cells = H.n_cells;
+    L.n_hanging = H.n_hanging_cells;
+    L.ent.upload(H.ent);
+    L.mask.upload(H.mask);
+    std::vector<int32_t> ijk(3 * H.n_cells);
+    for (int64_t c = 0; c < H.n_cells; ++c) {
+      ijk[3 * c] = static_cast<int32_t>(H.cells[c].i);
+      ijk[3 * c + 1] = static_cast<int32_t>(H.cells[c].j);
+      ijk[3 * c + 2] = static_cast<int32_t>(H.cells[c].k);
+    }
+    L.ijk.upload(ijk);
+    L.view.ent = L.ent.ptr;
+    L.view.mask = L.mask.ptr;
+    L.view.ijk = L.ijk.ptr;
+    L.view.n_cells = H.n_cells;
+    L.view.n_dofs = H.n_dofs;
+    L.view.n_shared = H.n_shared;
+    L.view.k = L.k;
+    L.view.h0 = H.h0;
+    L.view.lo = ctx.meshes[L.mesh].lo;
+    const int64_t nrhs = L.n_dofs * ctx.max_rhs;
+    const size_t sb = dtype_size(L.dtype);
+    L.x.alloc(nrhs * sb);
+    L.b.alloc(nrhs * sb);
+    L.r.alloc(nrhs * sb);
+    L.d.alloc(nrhs * 8);
+    L.t.alloc(nrhs * 8);
+    L.tmp_cast.alloc(nrhs * 8);
+    L.diag.alloc(L.n_dofs);
+    L.dinv.alloc(L.n_dofs * 8 * 2);  // double copy, then float copy
+    launch_diagonal(L.view, L.diag.ptr, s);
+    launch_inverse_diag(MFMG_F64, L.n_dofs, L.diag.ptr, L.dinv.ptr, s);
+    launch_inverse_diag(MFMG_F32, L.n_dofs, L.diag.ptr, L.dinv.ptr + L.n_dofs * 8, s);
+  }
+  for (int l = 1; l < nl; ++l) {
+    Level& L = ctx.levels[l];
+    const bool poly = ctx.levels[l - 1].mesh == L.mesh;
+    TransferDofs T = build_transfer(host[l], host[l - 1], poly);
+    L.has_transfer = true;
+    L.tr_ident_c.upload(T.ident_coarse);
+    L.tr_ident_f.upload(T.ident_fine);
+    L.tr_ref_c.upload(T.refined_coarse);
+    L.tr_ref_f.upload(T.refined_fine);
+    L.tr_valence.upload(T.valence);
+    L.tview.polynomial = poly;
+    L.tview.ident_coarse = L.tr_ident_c.ptr;
+    L.tview.ident_fine = L.tr_ident_f.ptr;
+    L.tview.n_ident = static_cast<int64_t>(T.ident_coarse.size());
+    L.tview.refined_coarse = L.tr_ref_c.ptr;
+    L.tview.refined_fine = L.tr_ref_f.ptr;
+    L.tview.n_refined = static_cast<int64_t>(T.refined_coarse.size());
+    L.tview.valence = L.tr_valence.ptr;
+  }
+  sync(s);
+  for (int l = 1; l < nl; ++l) estimate_eigenvalues(ctx, ctx.levels[l], eig_it, safety, range, s);
+  // exact coarse solver
+  {
+    Level& L0 = ctx.levels[0];
+    ctx.n0 = L0.n_dofs;
+    MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
+    std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k));
+    std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
+    std::vector<float> inv32(inv.begin(), inv.end());
+    ctx.coarse_inv64.upload(inv);
+    ctx.coarse_inv32.upload(inv32);
+  }
+  // PCG work space
+  const int64_t nf = ctx.fine().n_dofs * ctx.max_rhs;
+  ctx.cg_r.alloc(nf);
+  ctx.cg_p.alloc(nf);
+  ctx.cg_q.alloc(nf);
+  ctx.cg_z.alloc(nf);
+  ctx.cg_zold.alloc(nf);
+  ctx.cg_partial.alloc(static_cast<size_t>(dot_partials_needed()) * 8);
+  ctx.cg_scalar.alloc(8 * 8);
+  ctx.host_scalar.assign(8 * 8, 0.0);
+  sync(s);
+}
+
+// ---------------------------------------------------------------------------
+void level_vmult(Context& ctx, int l, int dtype, int nv, void* dst_acc, const void* src, hipStream_t s) {
+  Level& L = ctx.level(l);
+  launch_vmult(L.view, dtype, nv, dst_acc, src, s);
+}
+
+void level_smooth(Context& ctx, int l, int nv, void* x, const void* b, bool x_is_zero, double lmin, double lmax,
+                  hipStream_t s) {
+  Level& L = ctx.level(l);
+  const int dt = L.dtype;
+  const void* dinv = acc_dtype(dt) == MFMG_F64 ? static_cast<const void*>(L.dinv.ptr)
+                                               : static_cast<const void*>(L.dinv.ptr + L.n_dofs * 8);
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (x_is_zero) {
+    launch_cheb_step(dt, L.n_dofs, nv, true, 0.0, 1.0 / theta, nullptr, b, dinv, L.d.ptr, x, s);
+  } else {
+    launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
+    launch_cheb_step(dt, L.n_dofs, nv, false, 0.0, 1.0 / theta, L.t.ptr, b, dinv, L.d.ptr, x, s);
+  }
+  for (int it = 1; it < ctx.cheb_degree; ++it) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
+    launch_cheb_step(dt, L.n_dofs, nv, false, rho_new * rho, 2.0 * rho_new / delta, L.t.ptr, b, dinv, L.d.ptr, x, s);
+    rho = rho_new;
+  }
+}
+
+void level_residual(Context& ctx, int l, int nv, void* r, const void* b, const void* x, hipStream_t s) {
+  Level& L = ctx.level(l);
+  launch_vmult(L.view, L.dtype, nv, L.t.ptr, x, s);
+  launch_residual_update(L.dtype, L.n_dofs * nv, b, L.t.ptr, r, s);
+}
+
+void level_prolongate_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
+  MFMG_REQUIRE(fine >= 1 && fine < static_cast<int>(ctx.levels.size()), MFMG_ERR_INVALID_ARG, "fine level");
+  Level& F = ctx.levels[fine];
+  Level& C = ctx.levels[fine - 1];
+  launch_prolongate(F.view, C.view, F.tview, dtype, nv, dst, src, s);
+}
+
+void level_restrict_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
+  MFMG_REQUIRE(fine >= 1 && fine < static_cast<int>(ctx.levels.size()), MFMG_ERR_INVALID_ARG, "fine level");
+  Level& F = ctx.levels[fine];
+  Level& C = ctx.levels[fine - 1];
+  launch_restrict(F.view, C.view, F.tview, dtype, nv, dst, src, s);
+}
+
+void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipStream_t s) {
+  const void* inv = dtype == MFMG_F64 ? static_cast<const void*>(ctx.coarse_inv64.ptr)
+                                      : static_cast<const void*>(ctx.coarse_inv32.ptr);
+  launch_dense_matvec(dtype, ctx.n0, nv, inv, b, x, nullptr, s);
+}
+
+namespace {
+void vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
+  Level& L = ctx.levels[l];
+  if (l == 0) {
+    coarse_solve(ctx, L.dtype, nv, L.x.ptr, L.b.ptr, s);
+    return;
+  }
+  Level& C = ctx.levels[l - 1];
+  // presmoothing from x = 0
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, true, L.lmin, L.lmax, s);
+  // residual
+  level_residual(ctx, l, nv, L.r.ptr, L.b.ptr, L.x.ptr, s);
+  // restriction into a zeroed coarse right-hand side
+  launch_fill(0, C.b.ptr, C.n_dofs * nv * static_cast<int64_t>(dtype_size(C.dtype)), s);
+  if (C.dtype == L.dtype) {
+    level_restrict_add(ctx, l, L.dtype, nv, C.b.ptr, L.r.ptr, s);
+  } else {
+    launch_fill(0, C.tmp_cast.ptr, C.n_dofs * nv * static_cast<int64_t>(dtype_size(L.dtype)), s);
+    level_restrict_add(ctx, l, L.dtype, nv, C.tmp_cast.ptr, L.r.ptr, s);
+    launch_cast(L.dtype, C.dtype, C.n_dofs * nv, C.tmp_cast.ptr, C.b.ptr, s);
+  }
+  vcycle_level(ctx, l - 1, nv, s);
+  // prolongation
+  if (C.dtype == L.dtype) {
+    level_prolongate_add(ctx, l, L.dtype, nv, L.x.ptr, C.x.ptr, s);
+  } else {
+    launch_cast(C.dtype, L.dtype, C.n_dofs * nv, C.x.ptr, C.tmp_cast.ptr, s);
+    level_prolongate_add(ctx, l, L.dtype, nv, L.x.ptr, C.tmp_cast.ptr, s);
+  }
+  // postsmoothing
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, false, L.lmin, L.lmax, s);
+}
+}  // namespace
+
+void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s) {
+  MFMG_REQUIRE(nv >= 1 && nv <= ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+  Level& F = ctx.fine();
+  const int64_t n = F.n_dofs * nv;
+  launch_cast(MFMG_F64, F.dtype, n, b, F.b.ptr, s);  // copy_to_mg
+  vcycle_level(ctx, static_cast<int>(ctx.levels.size()) - 1, nv, s);
+  launch_cast(F.dtype, MFMG_F64, n, F.x.ptr, x, s);  // copy_from_mg
+}
+
+int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,
+        mfmg_solve_stats* stats, hipStream_t s) {
+  MFMG_REQUIRE(nv >= 1 && nv <= ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+  Level& F = ctx.fine();
+  const int64_t n = F.n_dofs;
+  const int64_t nn = n * nv;
+  double* sc = ctx.cg_scalar.ptr;  // [0..8) rz, [8..16) pq, [16..24) rr, [24..32) rz_new, [32..40) r.zold, [40..48) bb
+  double* rz = sc;
+  double* pq = sc + 8;
+  double* rr = sc + 16;
+  double* rzn = sc + 24;
+  double* rzo = sc + 32;
+  double* bb = sc + 40;
+  hipEvent_t e0, e1;
+  MFMG_HIP(hipEventCreate(&e0));
+  MFMG_HIP(hipEventCreate(&e1));
+  MFMG_HIP(hipEventRecord(e0, s));
+  launch_fill(0, x, nn * 8, s);
+  MFMG_HIP(hipMemcpyAsync(ctx.cg_r.ptr, b, nn * 8, hipMemcpyDeviceToDevice, s));
+  launch_dot(n, nv, b, b, ctx.cg_partial.ptr, bb, s);
+  std::vector<double> hb(nv), hr(nv);
+  MFMG_HIP(hipMemcpyAsync(hb.data(), bb, nv * 8, hipMemcpyDeviceToHost, s));
+  sync(s);
+  for (int v = 0; v < nv; ++v) hb[v] = std::sqrt(hb[v]);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->initial_residual = hb[0];
+    stats->residual_history[0] = 1.0;
+  }
+  bool all_zero = true;
+  for (int v = 0; v < nv; ++v) all_zero = all_zero && hb[v] == 0.0;
+  int status = MFMG_ERR_NOT_CONVERGED;
+  int it = 0;
+  double worst = 0.0;
+  if (all_zero) {
+    status = MFMG_OK;
+  } else {
+    vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
+    MFMG_HIP(hipMemcpyAsync(ctx.cg_p.ptr, ctx.cg_z.ptr, nn * 8, hipMemcpyDeviceToDevice, s));
+    launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_z.ptr, ctx.cg_partial.ptr, rz, s);
+    for (it = 1; it <= max_it; ++it) {
+      launch_vmult(F.view, MFMG_F64, nv, ctx.cg_q.ptr, ctx.cg_p.ptr, s);
+      launch_dot(n, nv, ctx.cg_p.ptr, ctx.cg_q.ptr, ctx.cg_partial.ptr, pq, s);
+      launch_cg_update_xr(n, nv, rz, pq, ctx.cg_p.ptr, ctx.cg_q.ptr, x, ctx.cg_r.ptr, s);
+      launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_r.ptr, ctx.cg_partial.ptr, rr, s);
+      std::vector<double> hpq(nv);
+      MFMG_HIP(hipMemcpyAsync(hr.data(), rr, nv * 8, hipMemcpyDeviceToHost, s));
+      MFMG_HIP(hipMemcpyAsync(hpq.data(), pq, nv * 8, hipMemcpyDeviceToHost, s));
+      sync(s);
+      worst = 0.0;
+      bool breakdown = false;
+      for (int v = 0; v < nv; ++v) {
+        const double rel = hb[v] > 0 ? std::sqrt(hr[v]) / hb[v] : 0.0;
+        worst = std::max(worst, rel);
+        if (hb[v] > 0 && !(hpq[v] > 0.0) && rel > rtol) breakdown = true;
+      }
+      if (stats && it < 256) stats->residual_history[it] = worst;
+      if (!std::isfinite(worst)) { status = MFMG_ERR_BREAKDOWN; break; }
+      if (worst <= rtol) { status = MFMG_OK; break; }
+      if (breakdown) { status = MFMG_ERR_BREAKDOWN; break; }
+      if (flexible) std::swap(ctx.cg_z.ptr, ctx.cg_zold.ptr);
+      vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
+      launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_z.ptr, ctx.cg_partial.ptr, rzn, s);
+      if (flexible) launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_zold.ptr, ctx.cg_partial.ptr, rzo, s);
+      launch_cg_update_p(n, nv, rzn, flexible ? rzo : nullptr, rz, ctx.cg_z.ptr, ctx.cg_p.ptr, s);
+      MFMG_HIP(hipMemcpyAsync(rz, rzn, nv * 8, hipMemcpyDeviceToDevice, s));
+    }
+    if (it > max_it) it = max_it;
+  }
+  MFMG_HIP(hipEventRecord(e1, s));
+  MFMG_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  MFMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (stats) {
+    stats->iterations = it;
+    stats->converged = status == MFMG_OK;
+    stats->final_residual = worst;
+    stats->time_ms = ms;
+  }
+  return status;
+}
+
+}  // namespace mfmg

@@ -1,0 +1,284 @@
+"""Thin ctypes binding of ``libmfmg.so`` (include/mfmg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Vectors are torch tensors on the GPU (``torch`` provides device memory and the
+current HIP stream); the library is required, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfmg.so")
+
+MFMG_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: "NOT_CONVERGED",
+          -6: "BREAKDOWN", -7: "NET_REJECTED"}
+F64, F32, BF16 = 0, 1, 2
+SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P = 0, 1, 2
+RHS_CONST, RHS_GAUSS = 0, 1
+MAX_STEPS, MAX_LEVELS = 16, 32
+
+
+class MfmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mfmg error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n0", C.c_int), ("lo", C.c_double), ("hi", C.c_double), ("n_global", C.c_int),
+                ("n_steps", C.c_int), ("kind", C.c_int * MAX_STEPS),
+                ("params", (C.c_double * 8) * MAX_STEPS)]
+
+
+class LevelDesc(C.Structure):
+    _fields_ = [("degree", C.c_int), ("scheme", C.c_int), ("dirichlet", C.c_int),
+                ("n_level_dtype", C.c_int), ("level_dtype", C.c_int * MAX_LEVELS),
+                ("cheb_degree", C.c_int), ("smoothing_range", C.c_double), ("eig_safety", C.c_double),
+                ("eig_iterations", C.c_int), ("max_rhs", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("initial_residual", C.c_double),
+                ("final_residual", C.c_double), ("residual_history", C.c_double * 256),
+                ("time_ms", C.c_double), ("coarse_fallbacks", C.c_int), ("coarse_accepted", C.c_int)]
+
+
+_lib = None
+_P = C.c_void_p
+_I = C.c_int
+_I64P = C.POINTER(C.c_int64)
+
+_SIGS = {
+    "mfmg_setup_mesh": (_I, [C.POINTER(MeshDesc), C.POINTER(_P)]),
+    "mfmg_mesh_info": (_I, [_P, C.POINTER(_I), _I64P, _I64P]),
+    "mfmg_host_level_matrix": (_I, [_P, _I, _I, _I, _I64P, _I64P, C.POINTER(C.c_double)]),
+    "mfmg_setup_levels": (_I, [_P, C.POINTER(LevelDesc), _P, C.POINTER(_P)]),
+    "mfmg_n_levels": (_I, [_P, C.POINTER(_I)]),
+    "mfmg_level_info": (_I, [_P, _I, _I64P, _I64P, C.POINTER(_I), C.POINTER(_I), _I64P]),
+    "mfmg_level_dof_codes": (_I, [_P, _I, _I64P]),
+    "mfmg_smoother_range": (_I, [_P, _I, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mfmg_vmult": (_I, [_P, _I, _I, _I, _P, _P, _P]),
+    "mfmg_diagonal": (_I, [_P, _I, _I, _P, _P]),
+    "mfmg_smooth": (_I, [_P, _I, _I, _I, _P, _P, _I, C.POINTER(C.c_double), _P]),
+    "mfmg_residual": (_I, [_P, _I, _I, _I, _P, _P, _P, _P]),
+    "mfmg_prolongate_add": (_I, [_P, _I, _I, _I, _P, _P, _P]),
+    "mfmg_restrict_add": (_I, [_P, _I, _I, _I, _P, _P, _P]),
+    "mfmg_coarse_solve": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mfmg_vcycle": (_I, [_P, _I, _P, _P, _P]),
+    "mfmg_solve": (_I, [_P, _I, _P, _P, C.c_double, _I, _I, C.POINTER(SolveStats), _P]),
+    "mfmg_rhs": (_I, [_P, _I, _I, C.POINTER(C.c_double), _I, _I, _P, _P]),
+    "mfmg_destroy_ctx": (None, [_P]),
+    "mfmg_destroy_mesh": (None, [_P]),
+    "mfmg_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load ``libmfmg.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2203_12292_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != MFMG_OK:
+        raise MfmgError(code, lib().mfmg_last_error().decode())
+    return code
+
+
+def mesh_desc(d):
+    """ctypes descriptor from a ``synth`` mesh descriptor dict."""
+    m = MeshDesc()
+    m.n0, m.lo, m.hi, m.n_global = d["n0"], d["lo"], d["hi"], d["n_global"]
+    m.n_steps = len(d["steps"])
+    for s, (kind, params) in enumerate(d["steps"]):
+        m.kind[s] = kind
+        for q, p in enumerate(params):
+            m.params[s][q] = p
+    return m
+
+
+def _dtype_code(t):
+    import torch
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    def __init__(self, desc):
+        self.handle = C.c_void_p()
+        self._desc = mesh_desc(desc) if isinstance(desc, dict) else desc
+        _check(lib().mfmg_setup_mesh(C.byref(self._desc), C.byref(self.handle)))
+
+    def info(self):
+        n = C.c_int()
+        _check(lib().mfmg_mesh_info(self.handle, C.byref(n), None, None))
+        cells = (C.c_int64 * n.value)()
+        nh = C.c_int64()
+        _check(lib().mfmg_mesh_info(self.handle, None, cells, C.byref(nh)))
+        return list(cells), nh.value
+
+    def host_level(self, mesh_index, degree, dirichlet=True, dense=False):
+        """(codes (n,3) int64, dense matrix or None) from the host set-up."""
+        n = C.c_int64()
+        _check(lib().mfmg_host_level_matrix(self.handle, mesh_index, degree, int(dirichlet), C.byref(n),
+                                            None, None))
+        codes = np.zeros((n.value, 3), dtype=np.int64)
+        A = np.zeros((n.value, n.value)) if dense else None
+        _check(lib().mfmg_host_level_matrix(
+            self.handle, mesh_index, degree, int(dirichlet), C.byref(n),
+            codes.ctypes.data_as(_I64P),
+            A.ctypes.data_as(C.POINTER(C.c_double)) if dense else None))
+        return codes, A
+
+    def close(self):
+        if self.handle:
+            lib().mfmg_destroy_mesh(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Multigrid levels on the GPU (``mfmg_setup_levels``) and the hot-path calls."""
+
+    def __init__(self, mesh, degree, scheme=SCHEME_H, level_dtypes=None, dirichlet=True, cheb_degree=3,
+                 max_rhs=1, smoothing_range=20.0, eig_safety=1.2, eig_iterations=15):
+        d = LevelDesc()
+        d.degree, d.scheme, d.dirichlet = degree, scheme, int(dirichlet)
+        level_dtypes = list(level_dtypes or [])
+        d.n_level_dtype = len(level_dtypes)
+        for i, t in enumerate(level_dtypes):
+            d.level_dtype[i] = t
+        d.cheb_degree, d.smoothing_range, d.eig_safety = cheb_degree, smoothing_range, eig_safety
+        d.eig_iterations, d.max_rhs = eig_iterations, max_rhs
+        self.desc = d
+        self.handle = C.c_void_p()
+        self.mesh = mesh
+        _check(lib().mfmg_setup_levels(mesh.handle, C.byref(d), _stream(), C.byref(self.handle)))
+        n = C.c_int()
+        _check(lib().mfmg_n_levels(self.handle, C.byref(n)))
+        self.n_levels = n.value
+
+    # -- information -----------------------------------------------------------
+    def level_info(self, level):
+        nd, nc, nh = C.c_int64(), C.c_int64(), C.c_int64()
+        k, dt = C.c_int(), C.c_int()
+        _check(lib().mfmg_level_info(self.handle, level, C.byref(nd), C.byref(nc), C.byref(k), C.byref(dt),
+                                     C.byref(nh)))
+        return {"n_dofs": nd.value, "n_cells": nc.value, "degree": k.value, "dtype": dt.value,
+                "n_hanging_cells": nh.value}
+
+    def n_dofs(self, level=None):
+        return self.level_info(self.n_levels - 1 if level is None else level)["n_dofs"]
+
+    def dof_codes(self, level):
+        n = self.n_dofs(level)
+        codes = np.zeros((n, 3), dtype=np.int64)
+        _check(lib().mfmg_level_dof_codes(self.handle, level, codes.ctypes.data_as(_I64P)))
+        return codes
+
+    def smoother_range(self, level):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().mfmg_smoother_range(self.handle, level, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # -- hot path (torch tensors on the GPU) -------------------------------------
+    def vmult(self, level, dst, src, n_vec=1):
+        _check(lib().mfmg_vmult(self.handle, level, _dtype_code(src), n_vec, _ptr(dst), _ptr(src), _stream()))
+        return dst
+
+    def diagonal(self, level, diag):
+        _check(lib().mfmg_diagonal(self.handle, level, _dtype_code(diag), _ptr(diag), _stream()))
+        return diag
+
+    def smooth(self, level, x, b, x_is_zero=False, lam=None, n_vec=1):
+        lp = (C.c_double * 2)(*lam) if lam is not None else None
+        _check(lib().mfmg_smooth(self.handle, level, _dtype_code(x), n_vec, _ptr(x), _ptr(b), int(x_is_zero),
+                                 lp, _stream()))
+        return x
+
+    def residual(self, level, r, b, x, n_vec=1):
+        _check(lib().mfmg_residual(self.handle, level, _dtype_code(r), n_vec, _ptr(r), _ptr(b), _ptr(x),
+                                   _stream()))
+        return r
+
+    def prolongate_add(self, fine_level, dst_fine, src_coarse, n_vec=1):
+        _check(lib().mfmg_prolongate_add(self.handle, fine_level, _dtype_code(dst_fine), n_vec, _ptr(dst_fine),
+                                         _ptr(src_coarse), _stream()))
+        return dst_fine
+
+    def restrict_add(self, fine_level, dst_coarse, src_fine, n_vec=1):
+        _check(lib().mfmg_restrict_add(self.handle, fine_level, _dtype_code(dst_coarse), n_vec,
+                                       _ptr(dst_coarse), _ptr(src_fine), _stream()))
+        return dst_coarse
+
+    def coarse_solve(self, x, b, n_vec=1):
+        _check(lib().mfmg_coarse_solve(self.handle, _dtype_code(x), n_vec, _ptr(x), _ptr(b), _stream()))
+        return x
+
+    def vcycle(self, x, b, n_vec=1):
+        _check(lib().mfmg_vcycle(self.handle, n_vec, _ptr(x), _ptr(b), _stream()))
+        return x
+
+    def solve(self, x, b, rtol=1e-10, max_it=100, flexible=False, n_vec=1, raise_on_fail=True):
+        st = SolveStats()
+        code = lib().mfmg_solve(self.handle, n_vec, _ptr(x), _ptr(b), rtol, max_it, int(flexible), C.byref(st),
+                                _stream())
+        if raise_on_fail:
+            _check(code)
+        hist = [st.residual_history[i] for i in range(min(st.iterations + 1, 256))]
+        return {"code": code, "iterations": st.iterations, "converged": bool(st.converged),
+                "initial_residual": st.initial_residual, "final_residual": st.final_residual,
+                "time_ms": st.time_ms, "history": hist, "coarse_fallbacks": st.coarse_fallbacks,
+                "coarse_accepted": st.coarse_accepted}
+
+    def rhs(self, b, kind=RHS_CONST, params=(1.0,), n_terms=0, n_vec=1, level=None):
+        level = self.n_levels - 1 if level is None else level
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+        _check(lib().mfmg_rhs(self.handle, level, kind, p.ctypes.data_as(C.POINTER(C.c_double)), n_terms, n_vec,
+                              _ptr(b), _stream()))
+        return b
+
+    def close(self):
+        if self.handle:
+            lib().mfmg_destroy_ctx(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exported_names():
+    """Function names declared in include/mfmg.h."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(_HERE), "include", "mfmg.h")).read()
+    return sorted(set(re.findall(r"\b(mfmg_[a-z0-9_]+)\s*\(", hdr)))
