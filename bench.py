@@ -1,0 +1,204 @@
+"""Benchmark: matrix-free operator throughput and time to solve on one MI355X.
+
+Workload (N=1): the Poisson problem on [0,1]^3, 16^3 coarse cubes refined
+four times towards the corner at the origin (cells with centre within 0.5),
+one-irregular, Q4 elements with 5^3 Gauss points: 1,068,726 cells, about 68M
+free DoFs.  A *step* is one application of the matrix-free operator of the
+finest level to a vector (gather with hanging-node constraints, sum
+factorisation, quadrature-point scaling, transposed steps, constrained
+scatter-add) in FP64, the paper's vmult.  ``value`` = free DoFs x steps / time
+of the timed region (inputs resident in HBM).  After the timed region the
+script solves the same problem to a relative residual of 1e-10 with the FP64
+V-cycle and with the FP32 V-cycle (FP64 CG), and reports both times; it also
+times the same-mesh plain FP64 solve, the mixed-precision variant (FP32 levels,
+bfloat16 on the two coarsest) on the 2808-cell Q2 mesh.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events_time(fn, k, stream):
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+    for i in range(k):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    return [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+
+def cpu_baseline(desc, k, target_seconds=15.0, max_cells=4000):
+    """The oracle's element-by-element operator (sum_e C_e^T A_e C_e x) timed
+    on a bounded sample of the workload's cells (set-up of the constraint rows
+    excluded, as the GPU set-up is)."""
+    import numpy as np
+
+    from oracle import fe, octree
+    from oracle.space import Space
+    tree = octree.build_mesh(desc)
+    S = Space(tree, k, build=False)
+    n_cells_total = len(S.cells)
+    rng = np.random.default_rng(0)
+    sample = [S.cells[i] for i in sorted(rng.choice(n_cells_total, size=min(max_cells, n_cells_total),
+                                                     replace=False))]
+    Aref = fe.reference_stiffness(k)
+    local = []
+    t_setup = time.time()
+    for cell in sample:
+        rows = S.cell_rows(cell)
+        keys = sorted({kk for row in rows for kk, _ in row})
+        pos = {kk: q for q, kk in enumerate(keys)}
+        C = np.zeros((len(rows), len(keys)))
+        for r, row in enumerate(rows):
+            for kk, v in row:
+                C[r, pos[kk]] += v
+        local.append((C, S.cell_h(cell) * Aref, len(keys)))
+        if time.time() - t_setup > 60:
+            break
+    x = [np.random.default_rng(i).uniform(-1, 1, m) for i, (_, _, m) in enumerate(local)]
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        passes = 0
+        while True:
+            for (C, Ae, _), xl in zip(local, x):
+                _ = C.T @ (Ae @ (C @ xl))
+            passes += 1
+            if time.time() - t0 >= target_seconds:
+                break
+        dt = time.time() - t0
+    return dt, passes, len(local), n_cells_total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-solves", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
+              "operator is a design in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2203_12292_amd import mfmg
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    desc = synth.CFG2
+    k = 4
+    t0 = time.time()
+    mesh = mfmg.Mesh(desc)
+    cells, n_hang = mesh.info()
+    solver = mfmg.Solver(mesh, k, mfmg.SCHEME_H_THEN_P)
+    setup_s = time.time() - t0
+    fine = solver.n_levels - 1
+    info = solver.level_info(fine)
+    n = info["n_dofs"]
+    x = torch.from_numpy(synth.uniform_vector(n, seed=12292)).to(dev)
+    y = torch.empty_like(x)
+
+    def op():
+        solver.vmult(fine, y, x)
+
+    for _ in range(args.warmup):
+        op()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ms = _events_time(op, args.steps, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    avg_ms = float(np.mean(ms))
+    value = n * args.steps / wall
+    alg_bytes = 16.0 * n  # read src + write dst, FP64 (metadata reported separately)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    # one plain copy of the same vector (calibration of the HBM byte counters)
+    y.copy_(x)
+    torch.cuda.synchronize()
+
+    out = {
+        "metric": "matrix-free vmult DoFs/s & %HBM peak; time-to-solve 1e-10, plain FP64 vs mixed/learned",
+        "value": value,
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson_cube16_ball4_q4", "cells": cells[-1], "free_dofs": n, "degree": k,
+                   "quadrature": "gauss 5^3", "hanging_cells": n_hang, "levels": solver.n_levels,
+                   "setup_s": round(setup_s, 2)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "vmult_batch_kernel + reduce_shared_kernel (one operator application)",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
+    }
+
+    if not args.skip_solves:
+        solves = {}
+        b = torch.zeros(n, dtype=torch.float64, device=dev)
+        solver.rhs(b)
+        xs = torch.zeros_like(b)
+        st = solver.solve(xs, b, rtol=1e-10, max_it=100)
+        st = solver.solve(xs, b, rtol=1e-10, max_it=100)
+        solves["cube16_q4_fp64"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                                    "residual": st["final_residual"]}
+        del solver
+        torch.cuda.empty_cache()
+        s32 = mfmg.Solver(mesh, k, mfmg.SCHEME_H_THEN_P, level_dtypes=[mfmg.F32])
+        st = s32.solve(xs, b, rtol=1e-10, max_it=100, flexible=True)
+        st = s32.solve(xs, b, rtol=1e-10, max_it=100, flexible=True)
+        solves["cube16_q4_fp32_vcycle"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                                           "residual": st["final_residual"]}
+        del s32
+        m1 = mfmg.Mesh(synth.CFG1)
+        for name, dts in (("cube4_q2_fp64", []), ("cube4_q2_mixed_bf16", [mfmg.BF16, mfmg.BF16, mfmg.F32])):
+            s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, level_dtypes=dts)
+            b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
+            s1.rhs(b1)
+            x1 = torch.zeros_like(b1)
+            for _ in range(3):
+                st = s1.solve(x1, b1, rtol=1e-10, max_it=100, flexible=bool(dts))
+            solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                            "residual": st["final_residual"]}
+        out["time_to_solve"] = solves
+
+    if not args.skip_cpu_baseline:
+        dt, passes, n_sample, n_total = cpu_baseline(desc, k)
+        dofs_per_cell = n / cells[-1]
+        v = passes * n_sample * dofs_per_cell / dt
+        out["cpu_baseline"] = {"value": v, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
+                               "sample": f"element-by-element C_e^T A_e C_e apply (numpy FP64, one thread) "
+                                         f"over {n_sample} random cells of the {n_total}-cell mesh, {passes} "
+                                         f"passes in {dt:.1f} s; DoFs/s = cells/s x {dofs_per_cell:.1f} "
+                                         f"free DoFs per cell"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -209,11 +209,66 @@ int mfmg_solve(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, double r
 /* Load vector b_i = int f phi_i (Gauss (k+1)^3 points, constraints
  * applied, Dirichlet rows 0) on level l in FP64.  kind 0: f = params[0];
  * kind 1: f = sum of n_terms Gaussians a exp(-|x-c|^2/(2w^2)), rows
- * (cx,cy,cz,w,a) in params (host memory), n_terms rows per vector.
+ * (cx,cy,cz,w,a) in params (host memory), n_terms rows per vector;
+ * kind 2: f = params[0] sin(params[1] x) sin(params[1] y) sin(params[1] z)
+ * (manufactured solutions).
  * Synchronises `stream` (params are staged through device memory). */
-enum { MFMG_RHS_CONST = 0, MFMG_RHS_GAUSS = 1 };
+enum { MFMG_RHS_CONST = 0, MFMG_RHS_GAUSS = 1, MFMG_RHS_SINE = 2 };
 int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_terms, int n_vec,
              void* b_f64, void* stream);
+
+/* [async] Constraint distribution (Section 3.1): the values of the FE
+ * function x (free DoFs, FP64) at every node of every cell, hanging nodes
+ * interpolated from their constraining DoFs and Dirichlet nodes 0.  out is
+ * [n_cells][(k+1)^3] (nodes lexicographic, x fastest) in the level's cell
+ * order; cell coordinates via mfmg_level_cells. */
+int mfmg_distribute(mfmg_ctx ctx, int level, const void* x_f64, void* out_f64, void* stream);
+
+/* Cells of a level in the library's order: levels[c] and ijk[3c..3c+2]
+ * (host arrays of n_cells and 3 n_cells entries). */
+int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk);
+
+/* ---- learned coarse correction (an extension, not in the paper) ---------
+ * A per-coarse-cell network replaces the exact coarse solve at level 0: input
+ * the coarse right-hand side at the cell's (k+1)^3 nodes divided by
+ * s = ||b0||_2 and the cell centre; two hidden layers of width 64 (GELU);
+ * output the cell's nodal correction divided by s; nodes of several cells
+ * average their cells' outputs.  The exact coarse solve judges every
+ * prediction: if ||b0 - A0 y||_2 > tau ||b0||_2 the exact solution is used.
+ * Flat FP32 parameters: W1 ((nq+3) x 64, row-major), b1, W2 (64x64), b2,
+ * W3 (64 x nq), b3, nq = (k+1)^3 of level 0.  Requires a coarse level
+ * without hanging nodes and at most 2048 DoFs. */
+enum { MFMG_COARSE_EXACT = 0, MFMG_COARSE_LEARNED = 1, MFMG_COARSE_ZERO = 2 };
+
+typedef struct {
+  int epochs;           /* passes over the data set */
+  int batch_rows;       /* rows (pairs x coarse cells) per Adam step, 0 -> 4096 */
+  double lr;            /* Adam step size, 0 -> 1e-3 (beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint64_t init_seed;   /* != 0: re-initialise parameters (He normal) from this seed */
+  uint64_t shuffle_seed;/* row order of the epochs */
+} mfmg_net_train_desc;
+
+int mfmg_net_n_params(mfmg_ctx ctx, int* n);
+/* Record the right-hand side reaching the coarse solver in every following
+ * V-cycle (up to `capacity` of them; 0 stops and frees). Synchronous. */
+int mfmg_net_record(mfmg_ctx ctx, int capacity);
+int mfmg_net_n_recorded(mfmg_ctx ctx, int* n);
+/* Copy parameters from/to host memory (n = mfmg_net_n_params). */
+int mfmg_net_set_params(mfmg_ctx ctx, const float* theta, int n);
+int mfmg_net_get_params(mfmg_ctx ctx, float* theta, int n);
+/* Mean squared error and its gradient (device FP32 arrays) over n_rows rows
+ * X [n_rows][nq+3], T [n_rows][nq] with the current parameters.  Synchronous. */
+int mfmg_net_loss_grad(mfmg_ctx ctx, int n_rows, const float* X, const float* T, float* grad, float* loss);
+/* Train on the recorded pairs (b0, A0^{-1} b0) with Adam on the GPU;
+ * history (host, `epochs` floats, may be NULL) gets the data-set loss after
+ * each epoch.  Synchronous. */
+int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history);
+/* Coarse solver of the V-cycle: MFMG_COARSE_EXACT, _LEARNED (with judge and
+ * fallback, threshold tau) or _ZERO (no coarse correction; for comparison). */
+int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau);
+/* Number of learned predictions accepted / rejected since the last call
+ * (resets both counters).  Synchronous. */
+int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected);
 
 /* ---- teardown ------------------------------------------------------------ */
 void mfmg_destroy_ctx(mfmg_ctx ctx);

@@ -5,6 +5,7 @@
 
 #include "context.hpp"
 #include "fe1d.hpp"
+#include "net.hpp"
 
 struct mfmg_ctx_s {
   mfmg::Context ctx;
@@ -94,7 +95,7 @@ int mfmg_host_level_matrix(mfmg_mesh mesh, int mesh_index, int degree, int diric
     check_ptr(n_dofs, "n_dofs");
     MFMG_REQUIRE(mesh_index >= 0 && mesh_index < static_cast<int>(mesh->gc.size()), MFMG_ERR_INVALID_ARG,
                  "mesh index");
-    mfmg::LevelDofs H = mfmg::build_level_dofs(mesh->gc[mesh_index], degree, dirichlet != 0);
+    mfmg::LevelDofs H = mfmg::build_level_dofs(mesh->gc[mesh_index], degree, dirichlet != 0, codes != nullptr);
     *n_dofs = H.n_dofs;
     if (codes) std::memcpy(codes, H.codes.data(), H.codes.size() * sizeof(int64_t));
     if (dense) {
@@ -185,8 +186,8 @@ int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const v
     check_nv(ctx->ctx, n_vec);
     MFMG_REQUIRE(dst != src, MFMG_ERR_INVALID_ARG, "dst and src must not alias");
     mfmg::Level& L = ctx->ctx.level(level);
+    MFMG_REQUIRE(n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
     if (dtype == MFMG_BF16) {
-      MFMG_REQUIRE(n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs for bfloat16");
       mfmg::launch_vmult(L.view, dtype, n_vec, L.t.ptr, src, as_stream(stream));
       mfmg::launch_acc_to_storage(dtype, L.n_dofs * n_vec, L.t.ptr, dst, as_stream(stream));
     } else {
@@ -320,15 +321,152 @@ int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_term
     check_ptr(b_f64, "b");
     check_ptr(params, "params");
     check_nv(ctx->ctx, n_vec);
-    MFMG_REQUIRE(kind == MFMG_RHS_CONST || kind == MFMG_RHS_GAUSS, MFMG_ERR_INVALID_ARG, "rhs kind");
-    MFMG_REQUIRE(kind == MFMG_RHS_CONST || n_terms >= 1, MFMG_ERR_INVALID_ARG, "n_terms");
+    MFMG_REQUIRE(kind == MFMG_RHS_CONST || kind == MFMG_RHS_GAUSS || kind == MFMG_RHS_SINE, MFMG_ERR_INVALID_ARG,
+                 "rhs kind");
+    MFMG_REQUIRE(kind != MFMG_RHS_GAUSS || n_terms >= 1, MFMG_ERR_INVALID_ARG, "n_terms");
     mfmg::Level& L = ctx->ctx.level(level);
-    const size_t np = kind == MFMG_RHS_CONST ? 1 : static_cast<size_t>(n_terms) * 5 * n_vec;
+    const size_t np = kind == MFMG_RHS_CONST ? 1 : kind == MFMG_RHS_SINE ? 2 : static_cast<size_t>(n_terms) * 5 * n_vec;
     mfmg::DeviceArray<double> dp;
     dp.upload(params, np);
-    mfmg::launch_rhs(L.view, kind, dp.ptr, kind == MFMG_RHS_CONST ? 0 : n_terms, n_vec,
+    mfmg::launch_rhs(L.view, kind, dp.ptr, kind == MFMG_RHS_GAUSS ? n_terms : 0, n_vec,
                      static_cast<double*>(b_f64), as_stream(stream));
     MFMG_HIP(hipStreamSynchronize(as_stream(stream)));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_distribute(mfmg_ctx ctx, int level, const void* x_f64, void* out_f64, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(x_f64, "x");
+    check_ptr(out_f64, "out");
+    mfmg::Level& L = ctx->ctx.level(level);
+    mfmg::launch_distribute(L.view, static_cast<const double*>(x_f64), static_cast<double*>(out_f64),
+                            as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (levels) std::memcpy(levels, L.host_levels.data(), L.host_levels.size() * sizeof(int32_t));
+    if (ijk) std::memcpy(ijk, L.host_ijk.data(), L.host_ijk.size() * sizeof(int32_t));
+    return MFMG_OK;
+  });
+}
+
+static void require_net(mfmg::Context& c) {
+  MFMG_REQUIRE(c.net.n_params > 0, MFMG_ERR_UNSUPPORTED,
+               "learned coarse correction needs a coarse level without hanging nodes and <= 2048 DoFs");
+}
+
+int mfmg_net_n_params(mfmg_ctx ctx, int* n) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(n, "n");
+    require_net(ctx->ctx);
+    *n = ctx->ctx.net.n_params;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_record(mfmg_ctx ctx, int capacity) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    require_net(ctx->ctx);
+    MFMG_REQUIRE(capacity >= 0, MFMG_ERR_INVALID_ARG, "capacity must be >= 0");
+    mfmg::NetState& N = ctx->ctx.net;
+    MFMG_HIP(hipDeviceSynchronize());
+    N.rec_capacity = capacity;
+    N.rec_count = 0;
+    if (capacity == 0) N.record.release();
+    else N.record.alloc(static_cast<size_t>(capacity) * N.n0);
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_n_recorded(mfmg_ctx ctx, int* n) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(n, "n");
+    *n = ctx->ctx.net.rec_count;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_set_params(mfmg_ctx ctx, const float* theta, int n) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(theta, "theta");
+    require_net(ctx->ctx);
+    MFMG_REQUIRE(n == ctx->ctx.net.n_params, MFMG_ERR_INVALID_ARG, "parameter count");
+    MFMG_HIP(hipMemcpy(ctx->ctx.net.params.ptr, theta, n * sizeof(float), hipMemcpyHostToDevice));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_get_params(mfmg_ctx ctx, float* theta, int n) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(theta, "theta");
+    require_net(ctx->ctx);
+    MFMG_REQUIRE(n == ctx->ctx.net.n_params, MFMG_ERR_INVALID_ARG, "parameter count");
+    MFMG_HIP(hipMemcpy(theta, ctx->ctx.net.params.ptr, n * sizeof(float), hipMemcpyDeviceToHost));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_loss_grad(mfmg_ctx ctx, int n_rows, const float* X, const float* T, float* grad, float* loss) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(X, "X");
+    check_ptr(T, "T");
+    check_ptr(grad, "grad");
+    require_net(ctx->ctx);
+    MFMG_REQUIRE(n_rows > 0, MFMG_ERR_INVALID_ARG, "n_rows must be > 0");
+    float l = mfmg::net_loss_grad(ctx->ctx, n_rows, X, T, grad, ctx->ctx.stream);
+    if (loss) *loss = l;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_ptr(desc, "desc");
+    require_net(ctx->ctx);
+    MFMG_REQUIRE(desc->epochs >= 1 && desc->batch_rows >= 0, MFMG_ERR_INVALID_ARG, "epochs/batch_rows");
+    mfmg::net_train(ctx->ctx, *desc, history, ctx->ctx.stream);
+    MFMG_HIP(hipStreamSynchronize(ctx->ctx.stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    MFMG_REQUIRE(mode == MFMG_COARSE_EXACT || mode == MFMG_COARSE_LEARNED || mode == MFMG_COARSE_ZERO,
+                 MFMG_ERR_INVALID_ARG, "coarse mode");
+    if (mode != MFMG_COARSE_EXACT) require_net(ctx->ctx);
+    MFMG_REQUIRE(tau >= 0, MFMG_ERR_INVALID_ARG, "tau must be >= 0");
+    ctx->ctx.net.mode = mode;
+    ctx->ctx.net.tau = tau;
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    require_net(ctx->ctx);
+    int c[2] = {0, 0};
+    MFMG_HIP(hipDeviceSynchronize());
+    MFMG_HIP(hipMemcpy(c, ctx->ctx.net.counters.ptr, 8, hipMemcpyDeviceToHost));
+    MFMG_HIP(hipMemset(ctx->ctx.net.counters.ptr, 0, 8));
+    if (accepted) *accepted = c[0];
+    if (rejected) *rejected = c[1];
     return MFMG_OK;
   });
 }

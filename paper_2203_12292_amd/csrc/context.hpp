@@ -22,7 +22,11 @@ struct Level {
   int dtype = MFMG_F64;
   int64_t n_dofs = 0, n_cells = 0, n_hanging = 0;
   DeviceArray<int32_t> ent, ijk;
+  std::vector<int32_t> host_levels, host_ijk;  // cell order of the level
   DeviceArray<uint32_t> mask;
+  DeviceArray<CellMeta> meta;
+  DeviceArray<int32_t> batch_cell, batch_sh, batch_ex, sh_idx, sh_pos, red_off;
+  DeviceArray<char> partial;
   CellView view;
   DeviceArray<double> diag;
   DeviceArray<char> dinv;  // 1/diag in the level's arithmetic type
@@ -36,6 +40,23 @@ struct Level {
   TransferView tview;
 };
 
+struct NetState {
+  int nq = 0, n_cells = 0, n0 = 0, n_params = 0;
+  DeviceArray<int32_t> node_dof;  // [n_cells][nq] coarse DoF of each cell node, -1 Dirichlet
+  DeviceArray<float> inv_val;     // 1 / number of coarse cells containing the DoF
+  DeviceArray<float> centre;      // [n_cells][3]
+  DeviceArray<float> params;
+  DeviceArray<double> work;
+  DeviceArray<int> counters;      // accepted, rejected
+  int mode = MFMG_COARSE_EXACT;
+  double tau = 0.5;
+  // recording of coarse right-hand sides
+  int rec_capacity = 0, rec_count = 0;
+  DeviceArray<double> record;
+  // training buffers
+  DeviceArray<float> X, T, z1, h1, z2, h2, y, d3, d2, d1, lossbuf;
+};
+
 struct Context {
   mfmg_level_desc desc{};
   std::vector<Octree> meshes;
@@ -45,6 +66,8 @@ struct Context {
   // exact coarse solver: dense inverse of A^(0)
   int64_t n0 = 0;
   DeviceArray<double> coarse_inv64;
+  DeviceArray<double> coarse_A64;
+  NetState net;
   DeviceArray<float> coarse_inv32;
   // FP64 CG work space on the finest level
   DeviceArray<double> cg_r, cg_p, cg_q, cg_z, cg_zold, cg_partial, cg_scalar;

@@ -74,7 +74,7 @@ struct EntityRec {
 
 bool LevelDofs::slot_hanging(int64_t c, int s) const { return mfmg::slot_hanging(mask[c], s); }
 
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet) {
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes) {
   MFMG_REQUIRE(k >= 1 && k <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   LevelDofs L;
   L.k = k;
@@ -143,12 +143,11 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet) {
     if (mask_hanging(m)) ++L.n_hanging_cells;
   }
 
-  // entities: numbering in first-touch order
+  // entities (ids only), first-touch order over the cells
   const int64_t dmax = static_cast<int64_t>(2 * tree.n0) << top;
   HashMap map(static_cast<size_t>(nc) * 8 + 64);
   std::vector<EntityRec> ents;
   ents.reserve(static_cast<size_t>(nc) * 8);
-  int64_t next = 0;
   for (int64_t c = 0; c < nc; ++c) {
     const Cell& x = cells[c];
     const uint32_t m = L.mask[c];
@@ -169,25 +168,140 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet) {
                            static_cast<uint64_t>(D[2]);
       bool inserted;
       int32_t id = map.find_or_insert(key, static_cast<int32_t>(ents.size()), inserted);
-      if (inserted) {
-        ents.push_back({owner.level, owner.i, owner.j, owner.k, s, static_cast<int32_t>(next)});
-        next += slot_size(s, k);
-        MFMG_REQUIRE(next < (1ll << 31), MFMG_ERR_UNSUPPORTED, "more than 2^31 DoFs on a level");
-      }
-      L.ent[s * nc + c] = ents[id].first_dof;
+      if (inserted) ents.push_back({owner.level, owner.i, owner.j, owner.k, s, -1});
       L.ent_id[s * nc + c] = id;
     }
   }
-  L.n_shared = next;
-  const int64_t nint = static_cast<int64_t>(k - 1) * (k - 1) * (k - 1);
-  MFMG_REQUIRE(next + nint * nc < (1ll << 31), MFMG_ERR_UNSUPPORTED, "more than 2^31 DoFs on a level");
+  const int64_t n_bent = static_cast<int64_t>(ents.size());  // boundary-of-cell entities
   for (int64_t c = 0; c < nc; ++c) {
-    L.ent[26 * nc + c] = static_cast<int32_t>(next + nint * c);
-    L.ent_id[26 * nc + c] = static_cast<int32_t>(ents.size() + c);
+    L.ent_id[26 * nc + c] = static_cast<int32_t>(n_bent + c);
+    ents.push_back({cells[c].level, cells[c].i, cells[c].j, cells[c].k, 26, -1});
   }
-  L.n_dofs = next + nint * nc;
-  L.n_entities = static_cast<int64_t>(ents.size()) + nc;
+  const int64_t ne = static_cast<int64_t>(ents.size());
+  L.n_entities = ne;
+  MFMG_REQUIRE(ne < (1ll << 31), MFMG_ERR_UNSUPPORTED, "too many entities");
+  auto esize = [&](int64_t id) { return slot_size(ents[id].slot, k); };
 
+  // batches: consecutive cells while the touched DoFs fit the LDS budget
+  const int mcap = batch_mcap(k);
+  std::vector<int32_t> stamp(ne, -1);
+  L.batch_cell_off.assign(1, 0);
+  {
+    int64_t local = 0, in_batch = 0;
+    int32_t b = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+      int64_t add = 0;
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id >= 0 && stamp[id] != b) add += esize(id);
+      }
+      if (in_batch > 0 && (local + add > mcap || in_batch >= BATCH_MAX_CELLS)) {
+        L.batch_cell_off.push_back(static_cast<int32_t>(c));
+        ++b;
+        local = 0;
+        in_batch = 0;
+        add = 0;
+        for (int s = 0; s < N_SLOTS; ++s) {
+          const int32_t id = L.ent_id[s * nc + c];
+          if (id >= 0 && stamp[id] != b) add += esize(id);
+        }
+      }
+      MFMG_REQUIRE(add <= mcap, MFMG_ERR_UNSUPPORTED, "cell exceeds the batch capacity");
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id >= 0 && stamp[id] != b) stamp[id] = b;
+      }
+      local += add;
+      ++in_batch;
+    }
+    if (nc > 0) L.batch_cell_off.push_back(static_cast<int32_t>(nc));
+  }
+  const int64_t nb = static_cast<int64_t>(L.batch_cell_off.size()) - 1;
+  L.n_batches = nb;
+
+  // shared (touched by >= 2 batches) or exclusive
+  std::vector<int32_t> n_touch(ne, 0);
+  std::fill(stamp.begin(), stamp.end(), -1);
+  for (int64_t b = 0; b < nb; ++b)
+    for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id < 0 || stamp[id] == static_cast<int32_t>(b)) continue;
+        stamp[id] = static_cast<int32_t>(b);
+        ++n_touch[id];
+      }
+
+  // numbering: shared entities first (first touch), then exclusive per batch
+  std::vector<int64_t> start(ne, -1);
+  int64_t next = 0;
+  for (int64_t c = 0; c < nc; ++c)
+    for (int s = 0; s < N_SLOTS; ++s) {
+      const int32_t id = L.ent_id[s * nc + c];
+      if (id < 0 || n_touch[id] < 2 || start[id] >= 0) continue;
+      start[id] = next;
+      next += esize(id);
+    }
+  L.n_shared = next;
+  L.batch_ex_off.assign(nb + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t ex0 = next;
+    for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id < 0 || n_touch[id] != 1 || start[id] >= 0) continue;
+        start[id] = next;
+        next += esize(id);
+      }
+    L.batch_ex_off[b + 1] = static_cast<int32_t>(L.batch_ex_off[b] + (next - ex0));
+  }
+  MFMG_REQUIRE(next < (1ll << 31), MFMG_ERR_UNSUPPORTED, "more than 2^31 DoFs on a level");
+  L.n_dofs = next;
+  for (int64_t c = 0; c < nc; ++c)
+    for (int s = 0; s < N_SLOTS; ++s) {
+      const int32_t id = L.ent_id[s * nc + c];
+      L.ent[s * nc + c] = id < 0 ? -1 : static_cast<int32_t>(start[id]);
+    }
+
+  // batch-local layout: shared entities (first touch in the batch), then the
+  // exclusive range in global order
+  L.loc.assign(static_cast<size_t>(N_SLOTS) * nc, 0xffff);
+  L.batch_sh_off.assign(nb + 1, 0);
+  std::vector<int32_t> lstart(ne, -1);
+  std::fill(stamp.begin(), stamp.end(), -1);
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t nsh = 0;
+    for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id < 0 || n_touch[id] < 2 || stamp[id] == static_cast<int32_t>(b)) continue;
+        stamp[id] = static_cast<int32_t>(b);
+        lstart[id] = static_cast<int32_t>(nsh);
+        for (int t = 0; t < esize(id); ++t) L.sh_idx.push_back(static_cast<int32_t>(start[id] + t));
+        nsh += esize(id);
+      }
+    L.batch_sh_off[b + 1] = static_cast<int32_t>(L.batch_sh_off[b] + nsh);
+    const int64_t ex_global = L.n_shared + L.batch_ex_off[b];
+    for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id < 0) continue;
+        const int64_t ls = n_touch[id] >= 2 ? lstart[id] : nsh + (start[id] - ex_global);
+        MFMG_REQUIRE(ls >= 0 && ls + esize(id) <= batch_mcap(k), MFMG_ERR_INVALID_ARG, "batch layout");
+        L.loc[s * nc + c] = static_cast<uint16_t>(ls);
+      }
+  }
+  // partial sums of shared DoF s at red_off[s] .. red_off[s+1]-1, in batch order
+  L.red_off.assign(L.n_shared + 1, 0);
+  for (int32_t g : L.sh_idx) ++L.red_off[g + 1];
+  for (int64_t i = 0; i < L.n_shared; ++i) L.red_off[i + 1] += L.red_off[i];
+  L.sh_pos.assign(L.sh_idx.size(), 0);
+  {
+    std::vector<int32_t> fill(L.red_off.begin(), L.red_off.end() - 1);
+    for (size_t p = 0; p < L.sh_idx.size(); ++p) L.sh_pos[p] = fill[L.sh_idx[p]]++;
+  }
+  for (size_t e = 0; e < ents.size(); ++e) ents[e].first_dof = static_cast<int32_t>(start[e]);
+
+  if (!want_codes) return L;
   // exact node codes of every DoF
   L.codes.assign(3 * L.n_dofs, 0);
   auto emit = [&](int lv, int64_t ci, int64_t cj, int64_t ck, int s, int64_t first) {
@@ -202,8 +316,8 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet) {
           ++dof;
         }
   };
-  for (const EntityRec& e : ents) emit(e.level, e.i, e.j, e.k, e.slot, e.first_dof);
-  for (int64_t c = 0; c < nc; ++c) emit(cells[c].level, cells[c].i, cells[c].j, cells[c].k, 26, next + nint * c);
+  for (const EntityRec& e : ents)
+    if (e.first_dof >= 0) emit(e.level, e.i, e.j, e.k, e.slot, e.first_dof);
   return L;
 }
 

@@ -5,10 +5,21 @@
 // vertex, an edge (k-1 DoFs), a face ((k-1)^2) or a cell interior ((k-1)^3).
 // Entities on the domain boundary carry homogeneous Dirichlet constraints and
 // have no DoFs.  Entities are identified by the doubled coordinates of their
-// centre on the finest lattice (unique across levels).  DoFs of vertices,
-// edges and faces ("shared" DoFs) are numbered first, entity by entity in the
-// order the cells (sorted along the Morton curve) first touch them; cell
-// interiors follow, cell by cell.
+// centre on the finest lattice (unique across levels).  The DoFs of one
+// entity are numbered consecutively.
+//
+// Cell batches (operator evaluation).  Consecutive cells along the Morton
+// curve are grouped into batches whose touched DoFs fit a fixed LDS budget.
+// An entity touched by one batch only is *exclusive*; otherwise *shared*.
+// The global numbering puts all shared DoFs first (first-touch order over the
+// batches), then the exclusive DoFs batch by batch, each batch's exclusive
+// DoFs forming one contiguous range.  A batch's local vector lists its shared
+// DoFs (explicit global indices) followed by its exclusive ones (a contiguous
+// copy of the global range).  Cells address it with 16-bit local entity
+// starts.  Shared DoFs receive one partial sum per touching batch; the
+// partial sums of shared DoF s occupy positions red_off[s] .. red_off[s+1]-1
+// of a partial buffer (`sh_pos` gives the position of each local shared DoF),
+// summed by a second pass.
 //
 // Gather maps with hanging-node constraints (Section 3.2: constraints applied
 // while the DoF values are set up, via an updated DoF map and in-place 1D
@@ -54,11 +65,21 @@ struct LevelDofs {
   std::vector<uint32_t> mask;     // per cell
   std::vector<int64_t> codes;     // [n_dofs][3]
   int64_t n_entities = 0;
+  // cell batches
+  int64_t n_batches = 0;
+  std::vector<int32_t> batch_cell_off;  // [n_batches+1]
+  std::vector<int32_t> batch_sh_off;    // [n_batches+1] into sh_idx / partial buffer
+  std::vector<int32_t> batch_ex_off;    // [n_batches+1] exclusive DoFs start at n_shared + batch_ex_off[b]
+  std::vector<int32_t> sh_idx;          // global DoF of each local shared DoF
+  std::vector<uint16_t> loc;            // [N_SLOTS][n_cells] local entity start, 0xffff Dirichlet
+  std::vector<int32_t> sh_pos;          // partial-buffer position of each local shared DoF
+  std::vector<int32_t> red_off;         // [n_shared+1]
   bool slot_hanging(int64_t c, int s) const;
 };
 
-// Builds the DoF numbering and gather maps of `tree` at degree k.
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet);
+// Builds the DoF numbering and gather maps of `tree` at degree k; `codes`
+// also computes the position codes of all DoFs.
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true);
 
 // Transfer data between a fine level and the next coarser one (Section 3.5).
 // Geometric: every coarse cell is a fine cell (identity category) or the

@@ -32,6 +32,36 @@ struct OpTab {
   T H[2][N * N];
 };
 
+// A symmetric, centrosymmetric n x n matrix (the 1D mass and stiffness
+// matrices on Gauss-Lobatto nodes) in even-odd form: with h = n/2,
+// e_j = x_j + x_{n-1-j}, o_j = x_j - x_{n-1-j} (j < h),
+//   y_i       = sum_j E_ij e_j + c_i x_h + sum_j O_ij o_j      (i < h)
+//   y_{n-1-i} = sum_j E_ij e_j + c_i x_h - sum_j O_ij o_j
+//   y_h       = sum_j c_j e_j + d x_h                          (n odd)
+// where E = (A_ij + A_i,n-1-j)/2 and O = (A_ij - A_i,n-1-j)/2 are symmetric
+// (upper triangles stored), c_i = A_ih, d = A_hh.
+template <typename T, int N>
+struct SymMat {
+  static constexpr int H = N / 2;
+  static constexpr int NE = H * (H + 1) / 2;
+  T e[NE > 0 ? NE : 1];
+  T o[NE > 0 ? NE : 1];
+  T c[H > 0 ? H : 1];
+  T d;
+};
+
+__host__ __device__ constexpr int sym_idx(int i, int j, int h) {
+  return i <= j ? i * h - i * (i - 1) / 2 + (j - i) : j * h - j * (j - 1) / 2 + (i - j);
+}
+
+// Operator tables: mass and stiffness in even-odd form (kernel arguments,
+// scalar registers) and the hanging-node interpolation (copied to LDS).
+template <typename T, int N>
+struct OpTab2 {
+  SymMat<T, N> M, K;
+  T Hg[2 * N * N];  // [s][i][j] = l_j((s + xi_i)/2)
+};
+
 template <typename T, int NF, int NC>
 struct TrTab {
   T P[NF * NC];     // 1D prolongation, row-major NF x NC
@@ -44,14 +74,6 @@ struct Gauss1D {
   double w[N];      // weights
   double S[N * N];  // S[q*N + i] = l_i(x_q)
 };
-
-template <int N> struct CPBOf { static constexpr int v = 1; };
-template <> struct CPBOf<2> { static constexpr int v = 64; };
-template <> struct CPBOf<3> { static constexpr int v = 28; };
-template <> struct CPBOf<4> { static constexpr int v = 16; };
-template <> struct CPBOf<5> { static constexpr int v = 10; };
-template <> struct CPBOf<6> { static constexpr int v = 7; };
-template <> struct CPBOf<7> { static constexpr int v = 5; };
 
 inline const Tables1D& tables(int k) {
   static Tables1D t[7] = {Tables1D(1), Tables1D(1), Tables1D(2), Tables1D(3),
@@ -82,6 +104,82 @@ OpTab<T, N> make_optab() {
     o.H[1][i] = static_cast<T>(t.H[1][i]);
   }
   return o;
+}
+
+template <typename T, int N>
+SymMat<T, N> make_sym(const std::vector<double>& A) {
+  SymMat<T, N> m{};
+  constexpr int H = N / 2;
+  for (int i = 0; i < H; ++i)
+    for (int j = i; j < H; ++j) {
+      m.e[sym_idx(i, j, H)] = static_cast<T>(0.5 * (A[i * N + j] + A[i * N + (N - 1 - j)]));
+      m.o[sym_idx(i, j, H)] = static_cast<T>(0.5 * (A[i * N + j] - A[i * N + (N - 1 - j)]));
+    }
+  if (N % 2) {
+    for (int i = 0; i < H; ++i) m.c[i] = static_cast<T>(A[i * N + H]);
+    m.d = static_cast<T>(A[H * N + H]);
+  }
+  return m;
+}
+
+template <typename T, int N>
+OpTab2<T, N> make_optab2() {
+  const Tables1D& t = tables(N - 1);
+  OpTab2<T, N> o;
+  o.M = make_sym<T, N>(t.M);
+  o.K = make_sym<T, N>(t.K);
+  for (int i = 0; i < N * N; ++i) {
+    o.Hg[i] = static_cast<T>(t.H[0][i]);
+    o.Hg[N * N + i] = static_cast<T>(t.H[1][i]);
+  }
+  return o;
+}
+
+// y = A x for a SymMat A (even-odd evaluation)
+template <int N, typename T>
+__device__ __forceinline__ void sym_mv(const SymMat<T, N>& A, const T (&x)[N], T (&y)[N]) {
+  constexpr int H = N / 2;
+  T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    e[j] = x[j] + x[N - 1 - j];
+    o[j] = x[j] - x[N - 1 - j];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T se = A.e[sym_idx(i, 0, H)] * e[0];
+    T so = A.o[sym_idx(i, 0, H)] * o[0];
+#pragma unroll
+    for (int j = 1; j < H; ++j) {
+      se += A.e[sym_idx(i, j, H)] * e[j];
+      so += A.o[sym_idx(i, j, H)] * o[j];
+    }
+    if constexpr (N % 2 == 1) se += A.c[i] * x[H];
+    y[i] = se + so;
+    y[N - 1 - i] = se - so;
+  }
+  if constexpr (N % 2 == 1) {
+    T m = A.d * x[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) m += A.c[j] * e[j];
+    y[H] = m;
+  }
+}
+
+// in-place hanging interpolation from the LDS table Hg: u <- H_s u (or H_s^T u)
+template <int N, typename T, bool TRANS>
+__device__ __forceinline__ void interp_lds(const T* __restrict__ Hg, int s, T (&u)[N]) {
+  const T* Hs = Hg + s * N * N;
+  T out[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc += Hs[TRANS ? j * N + i : i * N + j] * u[j];
+    out[i] = acc;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = out[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -162,27 +260,6 @@ __device__ __forceinline__ void add_to(S* p, T v, bool exclusive) {
   }
 }
 
-// gather of the line of nodes (a, b, 0..k) (along z), constraints not yet applied
-template <int K, typename S, typename T>
-__device__ __forceinline__ void gather_zline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell,
-                                             int a, int b, const S* __restrict__ src, int nv, int v,
-                                             T (&u)[K + 1]) {
-  const int s0 = node_slot(a, b, 0, K), s1 = node_slot(a, b, K, K);
-  const int o0 = node_offset(a, b, 0, K);
-  const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
-  u[0] = e0 < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e0 + o0) * nv + v]);
-  u[K] = e1 < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e1 + o0) * nv + v]);
-  if constexpr (K > 1) {
-    const int sm = node_slot(a, b, 1, K);
-    const int om = node_offset(a, b, 1, K);
-    const int st = K > 2 ? node_offset(a, b, 2, K) - om : 0;
-    const int32_t em = ent[sm * nc + cell];
-#pragma unroll
-    for (int c = 1; c < K; ++c)
-      u[c] = em < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(em + om + (c - 1) * st) * nv + v]);
-  }
-}
-
 // scatter-add of the line of nodes (a, 0..k, c) (along y); cell interiors are
 // owned by the cell (plain store), shared entities use atomics.
 template <int K, typename T>
@@ -211,14 +288,26 @@ __device__ __forceinline__ void scatter_yline(const int32_t* __restrict__ ent, i
   }
 }
 
+// Barrier of the cell pipeline.  All lanes of a cell belong to one
+// wavefront and LDS operations of a wavefront execute in order, so a compiler
+// code-motion barrier with wavefront-scope fences is enough.
+struct WaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // The cell pipeline C^T S^T Q S C on the block's LDS.  Input: this thread's
 // z-line (x = ta, y = tb) of gathered slot values.  Output: this thread's
 // y-line (x = ta, z = tb) of the result, before the scatter.  Must be called
 // by all threads of the block (contains barriers).
-template <int K, typename T>
+template <int K, typename T, typename Sync>
 __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict__ B1, bool active, uint32_t m,
                                               int block_hang, T h, const OpTab<T, K + 1>& tab, int ta, int tb,
                                               T (&u)[K + 1]) {
+  const Sync sync{};
   constexpr int N = K + 1, N2 = N * N;
   const bool hang = mask_hanging(m);
   // phase 1: z-lines (x = ta, y = tb): hanging z-interpolation, store
@@ -227,7 +316,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 #pragma unroll
     for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];
   }
-  __syncthreads();
+  sync();
   // phase 2: y-lines (x = ta, z = tb): hanging y-interpolation
   if (block_hang) {
     if (active && hang && hanging_line(m, 1, ta, tb, K)) {
@@ -237,7 +326,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 #pragma unroll
       for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
     }
-    __syncthreads();
+    sync();
   }
   // phase 3: x-lines (y = ta, z = tb): hanging x-interpolation, M_x, K_x
   T a[N], b[N];
@@ -253,7 +342,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
       B1[tb * N2 + ta * N + r] = b[r];
     }
   }
-  __syncthreads();
+  sync();
   // phase 4: y-lines (x = ta, z = tb): M_y a ; K_y a + M_y b
   if (active) {
 #pragma unroll
@@ -270,7 +359,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
       B1[tb * N2 + r * N + ta] = f[r];
     }
   }
-  __syncthreads();
+  sync();
   // phase 5: z-lines (x = ta, y = tb): h (K_z c + M_z f), transposed z-interpolation
   if (active) {
 #pragma unroll
@@ -285,7 +374,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 #pragma unroll
     for (int r = 0; r < N; ++r) B0[r * N2 + tb * N + ta] = u[r];
   }
-  __syncthreads();
+  sync();
   // phase 6: x-lines (y = ta, z = tb): transposed x-interpolation
   if (block_hang) {
     if (active && hang && hanging_line(m, 0, ta, tb, K)) {
@@ -295,7 +384,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 #pragma unroll
       for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
     }
-    __syncthreads();
+    sync();
   }
   // phase 7: y-lines (x = ta, z = tb): transposed y-interpolation
   if (active) {
@@ -305,26 +394,226 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
   }
 }
 
+// The cell pipeline with even-odd 1D operators and the hanging-node table in
+// LDS (`Hl`).  Same contract as cell_pipeline.
+template <int K, typename T, typename Sync>
+__device__ __forceinline__ void cell_pipeline2(T* __restrict__ B0, T* __restrict__ B1, bool active, uint32_t m,
+                                               int any_hang, T h, const OpTab2<T, K + 1>& tab,
+                                               const T* __restrict__ Hl, int ta, int tb, T (&u)[K + 1]) {
+  constexpr int N = K + 1, N2 = N * N;
+  const Sync sync{};
+  const bool hang = mask_hanging(m);
+  if (active) {
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, false>(Hl, mask_sub(m, 2), u);
+#pragma unroll
+    for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];
+  }
+  sync();
+  if (any_hang) {
+    if (active && hang && hanging_line(m, 1, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
+      interp_lds<N, T, false>(Hl, mask_sub(m, 1), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
+    }
+    sync();
+  }
+  T a[N], b[N];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
+    if (hang && hanging_line(m, 0, ta, tb, K)) interp_lds<N, T, false>(Hl, mask_sub(m, 0), u);
+    sym_mv<N>(tab.M, u, a);
+    sym_mv<N>(tab.K, u, b);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      B0[tb * N2 + ta * N + r] = a[r];
+      B1[tb * N2 + ta * N + r] = b[r];
+    }
+  }
+  sync();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      a[r] = B0[tb * N2 + r * N + ta];
+      b[r] = B1[tb * N2 + r * N + ta];
+    }
+    T c1[N], f1[N], f2[N];
+    sym_mv<N>(tab.M, a, c1);
+    sym_mv<N>(tab.K, a, f1);
+    sym_mv<N>(tab.M, b, f2);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      B0[tb * N2 + r * N + ta] = c1[r];
+      B1[tb * N2 + r * N + ta] = f1[r] + f2[r];
+    }
+  }
+  sync();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      a[r] = B0[r * N2 + tb * N + ta];
+      b[r] = B1[r * N2 + tb * N + ta];
+    }
+    T g1[N], g2[N];
+    sym_mv<N>(tab.K, a, g1);
+    sym_mv<N>(tab.M, b, g2);
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] = h * (g1[r] + g2[r]);
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, true>(Hl, mask_sub(m, 2), u);
+#pragma unroll
+    for (int r = 0; r < N; ++r) B0[r * N2 + tb * N + ta] = u[r];
+  }
+  sync();
+  if (any_hang) {
+    if (active && hang && hanging_line(m, 0, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
+      interp_lds<N, T, true>(Hl, mask_sub(m, 0), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
+    }
+    sync();
+  }
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
+    if (hang && hanging_line(m, 1, ta, tb, K)) interp_lds<N, T, true>(Hl, mask_sub(m, 1), u);
+  }
+}
+
+// Operator evaluation by cell batches.  One block per batch: the batch's
+// DoFs are loaded into LDS (shared DoFs through their index list, exclusive
+// DoFs as one contiguous range), the cells are evaluated group by group from
+// LDS and their contributions accumulated in LDS, then the exclusive DoFs are
+// stored contiguously and the shared DoFs written as this batch's partial
+// sums (reduced afterwards).  Consecutive batches run on the same XCD.
+__device__ __forceinline__ int64_t xcd_batch(int64_t bid, int64_t nb) {
+  const int64_t per = (nb + 7) / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
 template <int K, typename S, typename T>
-__global__ void __launch_bounds__(CPBOf<K + 1>::v * (K + 1) * (K + 1))
-    vmult_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc, double h0,
-                 OpTab<T, K + 1> tab, const S* __restrict__ src, T* __restrict__ dst, int nv) {
-  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPB = CPBOf<N>::v;
-  __shared__ T buf0[CPB * N3];
-  __shared__ T buf1[CPB * N3];
+__global__ void __launch_bounds__(BATCH_WAVES * 64)
+    vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
+                       const int32_t* __restrict__ bsh, const int32_t* __restrict__ bex,
+                       const int32_t* __restrict__ sh_idx, const int32_t* __restrict__ sh_pos, int64_t nb,
+                       int64_t n_shared, double h0, OpTab2<T, K + 1> tab, const S* __restrict__ src,
+                       T* __restrict__ partial,
+                       T* __restrict__ dst, int nv) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPW = cells_per_wave(N), MCAP = batch_mcap(K);
+  __shared__ T in_[MCAP];
+  __shared__ T out_[MCAP];
+  __shared__ T buf0[BATCH_WAVES * CPW * N3];
+  __shared__ T buf1[BATCH_WAVES * CPW * N3];
+  __shared__ T Hl[2 * N2];
+  const int64_t b = xcd_batch(blockIdx.x, nb);
+  if (b >= nb) return;
   const int v = blockIdx.y;
-  const int lc = threadIdx.x / N2;
-  const int t = threadIdx.x - lc * N2;
+  const int c0 = bcell[b], c1 = bcell[b + 1];
+  const int sh0 = bsh[b], nsh = bsh[b + 1] - sh0;
+  const int64_t ex0 = n_shared + bex[b];
+  const int m = nsh + (bex[b + 1] - bex[b]);
+  for (int i = threadIdx.x; i < 2 * N2; i += blockDim.x) Hl[i] = tab.Hg[i];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int64_t g = i < nsh ? static_cast<int64_t>(sh_idx[sh0 + i]) : ex0 + (i - nsh);
+    in_[i] = load_as<T>(src[g * nv + v]);
+    out_[i] = T(0);
+  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int lc = lane / N2;
+  const int t = lane - lc * N2;
+  const bool lane_used = lc < CPW;
   const int ta = t % N, tb = t / N;
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * CPB + lc;
-  const bool active = cell < nc;
-  const uint32_t m = active ? mask[cell] : 0u;
-  const int block_hang = __syncthreads_or(mask_hanging(m) ? 1 : 0);
-  const T h = static_cast<T>(ldexp(h0, -mask_level(m)));
-  T u[N];
-  if (active) gather_zline<K>(ent, nc, cell, ta, tb, src, nv, v, u);
-  cell_pipeline<K, T>(buf0 + lc * N3, buf1 + lc * N3, active, m, block_hang, h, tab, ta, tb, u);
-  if (active) scatter_yline<K>(ent, nc, cell, ta, tb, u, dst, nv, v);
+  T* B0 = buf0 + (wave * CPW + (lane_used ? lc : 0)) * N3;
+  T* B1 = buf1 + (wave * CPW + (lane_used ? lc : 0)) * N3;
+  // slots and offsets of this lane's gather line (x=ta, y=tb, z=0..k) and
+  // scatter line (x=ta, y=0..k, z=tb) do not depend on the cell
+  const int gs0 = node_slot(ta, tb, 0, K), gs1 = node_slot(ta, tb, K, K), gsm = node_slot(ta, tb, 1, K);
+  const int go0 = node_offset(ta, tb, 0, K), gom = node_offset(ta, tb, 1, K);
+  const int gst = K > 2 ? node_offset(ta, tb, 2, K) - gom : 0;
+  const int ss0 = node_slot(ta, 0, tb, K), ss1 = node_slot(ta, K, tb, K), ssm = node_slot(ta, 1, tb, K);
+  const int so0 = node_offset(ta, 0, tb, K), som = node_offset(ta, 1, tb, K);
+  const int sst = K > 2 ? node_offset(ta, 2, tb, K) - som : 0;
+  // metadata of this lane's cell, fetched one cell group ahead: the six
+  // local entity starts of its gather and scatter lines and the mask
+  struct Pre {
+    int g0, g1, gm, s0, s1, sm;
+    uint32_t mask;
+  };
+  auto fetch = [&](int64_t cell) {
+    Pre p{0xffff, 0xffff, 0xffff, 0xffff, 0xffff, 0xffff, 0u};
+    if (lane_used && cell < c1) {
+      const uint16_t* L = meta[cell].loc;
+      p.g0 = L[gs0];
+      p.g1 = L[gs1];
+      p.gm = L[gsm];
+      p.s0 = L[ss0];
+      p.s1 = L[ss1];
+      p.sm = L[ssm];
+      p.mask = meta[cell].mask;
+    }
+    return p;
+  };
+  int cw = c0 + wave * CPW;
+  Pre nx = fetch(cw + lc);
+  __syncthreads();
+  for (; cw < c1; cw += BATCH_WAVES * CPW) {
+    const int64_t cell = cw + lc;
+    const bool active = lane_used && cell < c1;
+    const Pre cur = nx;
+    nx = fetch(cw + BATCH_WAVES * CPW + lc);
+    const uint32_t mk = active ? cur.mask : 0u;
+    const int wave_hang = __any(mask_hanging(mk) ? 1 : 0);
+    const T h = static_cast<T>(ldexp(h0, -mask_level(mk)));
+    T u[N];
+    if (active) {
+      u[0] = cur.g0 == 0xffff ? T(0) : in_[cur.g0 + go0];
+      u[K] = cur.g1 == 0xffff ? T(0) : in_[cur.g1 + go0];
+      if constexpr (K > 1) {
+#pragma unroll
+        for (int c = 1; c < K; ++c) u[c] = cur.gm == 0xffff ? T(0) : in_[cur.gm + gom + (c - 1) * gst];
+      }
+    }
+    cell_pipeline2<K, T, WaveSync>(B0, B1, active, mk, wave_hang, h, tab, Hl, ta, tb, u);
+    if (active) {
+      if (cur.s0 != 0xffff) atomicAdd(&out_[cur.s0 + so0], u[0]);
+      if (cur.s1 != 0xffff) atomicAdd(&out_[cur.s1 + so0], u[K]);
+      if constexpr (K > 1) {
+        if (cur.sm != 0xffff) {
+          if (ssm == 26) {
+#pragma unroll
+            for (int r = 1; r < K; ++r) out_[cur.sm + som + (r - 1) * sst] = u[r];
+          } else {
+#pragma unroll
+            for (int r = 1; r < K; ++r) atomicAdd(&out_[cur.sm + som + (r - 1) * sst], u[r]);
+          }
+        }
+      }
+    }
+    WaveSync{}();  // the next cell group reuses this wavefront's buffers
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    if (i < nsh) partial[static_cast<int64_t>(sh_pos[sh0 + i]) * nv + v] = out_[i];
+    else dst[(ex0 + (i - nsh)) * nv + v] = out_[i];
+  }
+}
+
+// dst[s] = sum of the partial sums of shared DoF s (fixed order)
+template <typename T>
+__global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __restrict__ red_off,
+                                     const T* __restrict__ partial, T* __restrict__ dst) {
+  const int64_t n = n_shared * nv;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t sd = i / nv;
+    const int v = static_cast<int>(i - sd * nv);
+    T acc = T(0);
+    for (int j = red_off[sd]; j < red_off[sd + 1]; ++j) acc += partial[static_cast<int64_t>(j) * nv + v];
+    dst[i] = acc;
+  }
 }
 
 // Diagonal (Eq. impl:mf:diagonal).  Cells without constraints: d_e(i) =
@@ -356,16 +645,55 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
       double u[N];
 #pragma unroll
       for (int c = 0; c < N; ++c) u[c] = (ta == sa && tb == sb && c == sc) ? 1.0 : 0.0;
-      cell_pipeline<K, double>(B0, B1, true, m, 1, h, tab, ta, tb, u);
+      cell_pipeline<K, double, WaveSync>(B0, B1, true, m, 1, h, tab, ta, tb, u);
       if (ta == sa && tb == sc) {
 #pragma unroll
         for (int r = 0; r < N; ++r)
           if (r == sb) d[r] += u[r];
       }
-      __syncthreads();
+      WaveSync{}();
     }
   }
   scatter_yline<K>(ent, nc, cell, ta, tb, d, diag, 1, 0);
+}
+
+// Constraint distribution: gather G_e and hanging-node interpolation C_e of
+// one cell, written out node by node.  One cell per block, n^2 threads.
+template <int K>
+__global__ void __launch_bounds__((K + 1) * (K + 1))
+    distribute_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
+                      OpTab<double, K + 1> tab, const double* __restrict__ x, double* __restrict__ out) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
+  __shared__ double B[N3];
+  const int64_t cell = blockIdx.x;
+  const int ta = threadIdx.x % N, tb = threadIdx.x / N;
+  const uint32_t m = mask[cell];
+  double u[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const int s = node_slot(ta, tb, c, K);
+    const int32_t e = ent[s * nc + cell];
+    u[c] = e < 0 ? 0.0 : x[e + node_offset(ta, tb, c, K)];
+  }
+  const bool hang = mask_hanging(m);
+  if (hang && hanging_line(m, 2, ta, tb, K)) interp<N, double, false>(tab.H, mask_sub(m, 2), u);
+#pragma unroll
+  for (int c = 0; c < N; ++c) B[c * N2 + tb * N + ta] = u[c];
+  __syncthreads();
+  // y-lines (x = ta, z = tb)
+#pragma unroll
+  for (int r = 0; r < N; ++r) u[r] = B[tb * N2 + r * N + ta];
+  if (hang && hanging_line(m, 1, ta, tb, K)) interp<N, double, false>(tab.H, mask_sub(m, 1), u);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[tb * N2 + r * N + ta] = u[r];
+  __syncthreads();
+  // x-lines (y = ta, z = tb)
+#pragma unroll
+  for (int r = 0; r < N; ++r) u[r] = B[tb * N2 + ta * N + r];
+  if (hang && hanging_line(m, 0, ta, tb, K)) interp<N, double, false>(tab.H, mask_sub(m, 0), u);
+#pragma unroll
+  for (int r = 0; r < N; ++r) out[cell * N3 + tb * N2 + ta * N + r] = u[r];
 }
 
 // Load vector b_e = int_e f phi (Gauss (k+1)^3), then C_e^T and scatter.
@@ -395,6 +723,8 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
     double f = 0.0;
     if (kind == 0) {
       f = params[0];
+    } else if (kind == 2) {
+      f = params[0] * sin(params[1] * x) * sin(params[1] * y) * sin(params[1] * z);
     } else {
       const double* p = params + static_cast<int64_t>(v) * n_terms * 5;
       for (int t = 0; t < n_terms; ++t) {
@@ -834,14 +1164,20 @@ void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
 template <int K, typename S>
 void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t s) {
   using T = typename Acc<S>::type;
-  constexpr int N = K + 1, CPB = CPBOf<N>::v;
-  zero_bytes(dst, c.n_shared * nv * static_cast<int64_t>(sizeof(T)), s);
+  constexpr int N = K + 1;
   if (c.n_cells == 0) return;
-  static const OpTab<T, N> tab = make_optab<T, N>();
-  dim3 grid(static_cast<unsigned>((c.n_cells + CPB - 1) / CPB), nv);
-  vmult_kernel<K, S, T><<<grid, CPB * N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab,
-                                                    static_cast<const S*>(src), static_cast<T*>(dst), nv);
+  static const OpTab2<T, N> tab = make_optab2<T, N>();
+  const int64_t nb = c.n_batches;
+  dim3 grid(static_cast<unsigned>(8 * ((nb + 7) / 8)), nv);
+  vmult_batch_kernel<K, S, T><<<grid, BATCH_WAVES * 64, 0, s>>>(
+      c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, c.sh_pos, nb, c.n_shared, c.h0, tab,
+      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv);
   check_launch();
+  if (c.n_shared > 0) {
+    reduce_shared_kernel<T><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
+        c.n_shared, nv, c.red_off, static_cast<const T*>(c.partial), static_cast<T*>(dst));
+    check_launch();
+  }
 }
 
 template <typename S>
@@ -860,7 +1196,7 @@ void vmult_s(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
 template <int K>
 void diag_k(const CellView& c, double* diag, hipStream_t s) {
   constexpr int N = K + 1;
-  zero_bytes(diag, c.n_shared * 8, s);
+  zero_bytes(diag, c.n_dofs * 8, s);
   if (c.n_cells == 0) return;
   static const OpTab<double, N> tab = make_optab<double, N>();
   diag_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab, diag);
@@ -870,7 +1206,7 @@ void diag_k(const CellView& c, double* diag, hipStream_t s) {
 template <int K>
 void rhs_k(const CellView& c, int kind, const double* params, int n_terms, int nv, double* b, hipStream_t s) {
   constexpr int N = K + 1;
-  zero_bytes(b, c.n_shared * nv * 8, s);
+  zero_bytes(b, c.n_dofs * nv * 8, s);
   if (c.n_cells == 0) return;
   static const OpTab<double, N> tab = make_optab<double, N>();
   static const Gauss1D<N> g = make_gauss<N>();
@@ -979,6 +1315,27 @@ void launch_diagonal(const CellView& c, double* diag, hipStream_t s) {
     case 4: diag_k<4>(c, diag, s); break;
     case 5: diag_k<5>(c, diag, s); break;
     case 6: diag_k<6>(c, diag, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
+  }
+}
+
+template <int K>
+void distribute_k(const CellView& c, const double* x, double* out, hipStream_t s) {
+  constexpr int N = K + 1;
+  if (c.n_cells == 0) return;
+  static const OpTab<double, N> tab = make_optab<double, N>();
+  distribute_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(c.ent, c.mask, c.n_cells, tab, x, out);
+  check_launch();
+}
+
+void launch_distribute(const CellView& c, const double* x, double* out, hipStream_t s) {
+  switch (c.k) {
+    case 1: distribute_k<1>(c, x, out, s); break;
+    case 2: distribute_k<2>(c, x, out, s); break;
+    case 3: distribute_k<3>(c, x, out, s); break;
+    case 4: distribute_k<4>(c, x, out, s); break;
+    case 5: distribute_k<5>(c, x, out, s); break;
+    case 6: distribute_k<6>(c, x, out, s); break;
     default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
   }
 }

@@ -7,6 +7,15 @@
 
 namespace mfmg {
 
+// Per-cell record of the operator (one 64-byte line): local entity starts of
+// the 27 slots in the batch's LDS vector (0xffff: Dirichlet) and the mask.
+struct alignas(64) CellMeta {
+  uint16_t loc[28];
+  uint32_t mask;
+  uint32_t pad;
+};
+static_assert(sizeof(CellMeta) == 64, "CellMeta must be one 64-byte line");
+
 // Per-level device view of the cell data.
 struct CellView {
   const int32_t* ent = nullptr;  // [27][n_cells]
@@ -18,6 +27,16 @@ struct CellView {
   int k = 1;
   double h0 = 1.0;  // coarse-grid cell size
   double lo = 0.0;  // domain lower corner
+  // cell batches of the operator (see dofs.hpp)
+  int64_t n_batches = 0;
+  const CellMeta* meta = nullptr;     // [n_cells]
+  const int32_t* batch_cell = nullptr;
+  const int32_t* batch_sh = nullptr;
+  const int32_t* batch_ex = nullptr;
+  const int32_t* sh_idx = nullptr;
+  const int32_t* sh_pos = nullptr;
+  const int32_t* red_off = nullptr;
+  void* partial = nullptr;            // scratch: partial sums, (sh_idx size) x max_rhs x 8 bytes
 };
 
 struct TransferView {
@@ -34,7 +53,7 @@ struct TransferView {
 // dtype: MFMG_F64 / MFMG_F32 / MFMG_BF16 for the vectors named "S"; the
 // "acc" vectors are double for F64 and float otherwise.
 
-// dst_acc = A src  (dst zeroed here on the shared range, interiors overwritten)
+// dst_acc = A src (every entry written; no initialisation needed)
 void launch_vmult(const CellView& c, int dtype, int nv, void* dst_acc, const void* src, hipStream_t s);
 // diag (FP64) = diagonal of A
 void launch_diagonal(const CellView& c, double* diag, hipStream_t s);
@@ -47,6 +66,9 @@ void launch_prolongate(const CellView& fine, const CellView& coarse, const Trans
 // dst_coarse (S) += P^T src_fine (S)
 void launch_restrict(const CellView& fine, const CellView& coarse, const TransferView& t, int dtype, int nv,
                      void* dst_coarse, const void* src_fine, hipStream_t s);
+
+// out[c][n^3] = node values of cell c (constraints applied) for x (FP64)
+void launch_distribute(const CellView& c, const double* x, double* out, hipStream_t s);
 
 // ---- vector kernels (n = number of entries, i.e. n_dofs * nv) --------------
 void launch_fill(int dtype_bytes, void* x, int64_t n_bytes, hipStream_t s);

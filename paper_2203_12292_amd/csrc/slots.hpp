@@ -56,6 +56,30 @@ __host__ __device__ constexpr int slot_size(int s, int k) {
   return s < 8 ? 1 : s < 20 ? km : s < 26 ? km * km : km * km * km;
 }
 
+// Operator kernels: a cell is handled by n^2 lanes of one wavefront (one
+// lane per line of n nodes), cells_per_wave(n) = floor(64 / n^2) cells per
+// wavefront, BATCH_WAVES wavefronts per block.
+#ifndef MFMG_BATCH_WAVES
+#define MFMG_BATCH_WAVES 8
+#endif
+constexpr int BATCH_WAVES = MFMG_BATCH_WAVES;
+__host__ __device__ constexpr int cells_per_wave(int n) { return 64 / (n * n); }
+
+// Cell batches of the operator: a batch's DoFs are staged in LDS (input and
+// accumulated output, FP64) next to the per-wave work buffers, within
+// BATCH_LDS_BYTES per block.  batch_mcap(k) bounds the DoFs a batch touches.
+#ifndef MFMG_BATCH_LDS_BYTES
+#define MFMG_BATCH_LDS_BYTES 81920
+#endif
+constexpr int BATCH_LDS_BYTES = MFMG_BATCH_LDS_BYTES;
+constexpr int BATCH_MAX_CELLS = 1024;
+__host__ __device__ constexpr int batch_work_bytes(int k) {
+  return BATCH_WAVES * cells_per_wave(k + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8;
+}
+__host__ __device__ constexpr int batch_mcap(int k) {
+  return ((BATCH_LDS_BYTES - batch_work_bytes(k)) / 16) / 64 * 64;
+}
+
 // Mask bits.
 __host__ __device__ inline int mask_sub(uint32_t m, int d) { return (m >> d) & 1; }
 __host__ __device__ inline int mask_face(uint32_t m, int d) { return (m >> (3 + d)) & 1; }

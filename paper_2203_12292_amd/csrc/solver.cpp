@@ -8,6 +8,7 @@
 
 #include "context.hpp"
 #include "fe1d.hpp"
+#include "net.hpp"
 
 namespace mfmg {
 
@@ -209,7 +210,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     if (desc.n_level_dtype <= 0) L.dtype = MFMG_F64;
     else L.dtype = desc.level_dtype[std::min(l, desc.n_level_dtype - 1)];
     MFMG_REQUIRE(L.dtype >= MFMG_F64 && L.dtype <= MFMG_BF16, MFMG_ERR_UNSUPPORTED, "level dtype");
-    host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0);
+    host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false);
     const LevelDofs& H = host[l];
     L.n_dofs = H.n_dofs;
     L.n_cells = H.n_cells;
@@ -223,6 +224,9 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
       ijk[3 * c + 2] = static_cast<int32_t>(H.cells[c].k);
     }
     L.ijk.upload(ijk);
+    L.host_ijk = ijk;
+    L.host_levels.resize(H.n_cells);
+    for (int64_t c = 0; c < H.n_cells; ++c) L.host_levels[c] = H.cells[c].level;
     L.view.ent = L.ent.ptr;
     L.view.mask = L.mask.ptr;
     L.view.ijk = L.ijk.ptr;
@@ -232,6 +236,32 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     L.view.k = L.k;
     L.view.h0 = H.h0;
     L.view.lo = ctx.meshes[L.mesh].lo;
+    {
+      std::vector<CellMeta> meta(H.n_cells);
+      for (int64_t c = 0; c < H.n_cells; ++c) {
+        for (int sl = 0; sl < N_SLOTS; ++sl) meta[c].loc[sl] = H.loc[sl * H.n_cells + c];
+        meta[c].loc[27] = 0xffff;
+        meta[c].mask = H.mask[c];
+        meta[c].pad = 0;
+      }
+      L.meta.upload(meta);
+    }
+    L.batch_cell.upload(H.batch_cell_off);
+    L.batch_sh.upload(H.batch_sh_off);
+    L.batch_ex.upload(H.batch_ex_off);
+    L.sh_idx.upload(H.sh_idx);
+    L.sh_pos.upload(H.sh_pos);
+    L.red_off.upload(H.red_off);
+    L.partial.alloc(std::max<size_t>(1, H.sh_idx.size()) * ctx.max_rhs * 8);
+    L.view.n_batches = H.n_batches;
+    L.view.meta = L.meta.ptr;
+    L.view.batch_cell = L.batch_cell.ptr;
+    L.view.batch_sh = L.batch_sh.ptr;
+    L.view.batch_ex = L.batch_ex.ptr;
+    L.view.sh_idx = L.sh_idx.ptr;
+    L.view.sh_pos = L.sh_pos.ptr;
+    L.view.red_off = L.red_off.ptr;
+    L.view.partial = L.partial.ptr;
     const int64_t nrhs = L.n_dofs * ctx.max_rhs;
     const size_t sb = dtype_size(L.dtype);
     L.x.alloc(nrhs * sb);
@@ -273,11 +303,14 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     ctx.n0 = L0.n_dofs;
     MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
     std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k));
+    ctx.coarse_A64.upload(A);
     std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
     std::vector<float> inv32(inv.begin(), inv.end());
     ctx.coarse_inv64.upload(inv);
     ctx.coarse_inv32.upload(inv32);
   }
+  // learned coarse correction (available for small coarse levels without hanging nodes)
+  if (ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0) net_setup(ctx, host[0]);
   // PCG work space
   const int64_t nf = ctx.fine().n_dofs * ctx.max_rhs;
   ctx.cg_r.alloc(nf);
@@ -350,7 +383,13 @@ namespace {
 void vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
   Level& L = ctx.levels[l];
   if (l == 0) {
-    coarse_solve(ctx, L.dtype, nv, L.x.ptr, L.b.ptr, s);
+    NetState& N = ctx.net;
+    if (N.rec_count < N.rec_capacity && nv == 1) {
+      launch_cast(L.dtype, MFMG_F64, L.n_dofs, L.b.ptr, N.record.ptr + static_cast<int64_t>(N.rec_count) * L.n_dofs, s);
+      ++N.rec_count;
+    }
+    if (N.mode != MFMG_COARSE_EXACT && nv == 1) net_coarse_solve(ctx, L.dtype, L.x.ptr, L.b.ptr, s);
+    else coarse_solve(ctx, L.dtype, nv, L.x.ptr, L.b.ptr, s);
     return;
   }
   Level& C = ctx.levels[l - 1];

@@ -19,7 +19,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: 
           -6: "BREAKDOWN", -7: "NET_REJECTED"}
 F64, F32, BF16 = 0, 1, 2
 SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P = 0, 1, 2
-RHS_CONST, RHS_GAUSS = 0, 1
+RHS_CONST, RHS_GAUSS, RHS_SINE = 0, 1, 2
+COARSE_EXACT, COARSE_LEARNED, COARSE_ZERO = 0, 1, 2
 MAX_STEPS, MAX_LEVELS = 16, 32
 
 
@@ -40,6 +41,11 @@ class LevelDesc(C.Structure):
                 ("n_level_dtype", C.c_int), ("level_dtype", C.c_int * MAX_LEVELS),
                 ("cheb_degree", C.c_int), ("smoothing_range", C.c_double), ("eig_safety", C.c_double),
                 ("eig_iterations", C.c_int), ("max_rhs", C.c_int)]
+
+
+class NetTrainDesc(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch_rows", C.c_int), ("lr", C.c_double), ("init_seed", C.c_uint64),
+                ("shuffle_seed", C.c_uint64)]
 
 
 class SolveStats(C.Structure):
@@ -72,6 +78,17 @@ _SIGS = {
     "mfmg_vcycle": (_I, [_P, _I, _P, _P, _P]),
     "mfmg_solve": (_I, [_P, _I, _P, _P, C.c_double, _I, _I, C.POINTER(SolveStats), _P]),
     "mfmg_rhs": (_I, [_P, _I, _I, C.POINTER(C.c_double), _I, _I, _P, _P]),
+    "mfmg_distribute": (_I, [_P, _I, _P, _P, _P]),
+    "mfmg_level_cells": (_I, [_P, _I, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "mfmg_net_n_params": (_I, [_P, C.POINTER(_I)]),
+    "mfmg_net_record": (_I, [_P, _I]),
+    "mfmg_net_n_recorded": (_I, [_P, C.POINTER(_I)]),
+    "mfmg_net_set_params": (_I, [_P, C.POINTER(C.c_float), _I]),
+    "mfmg_net_get_params": (_I, [_P, C.POINTER(C.c_float), _I]),
+    "mfmg_net_loss_grad": (_I, [_P, _I, _P, _P, _P, C.POINTER(C.c_float)]),
+    "mfmg_net_train": (_I, [_P, C.POINTER(NetTrainDesc), C.POINTER(C.c_float)]),
+    "mfmg_net_mode": (_I, [_P, _I, C.c_double]),
+    "mfmg_net_counts": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
     "mfmg_destroy_ctx": (None, [_P]),
     "mfmg_destroy_mesh": (None, [_P]),
     "mfmg_last_error": (C.c_char_p, []),
@@ -264,6 +281,61 @@ class Solver:
         _check(lib().mfmg_rhs(self.handle, level, kind, p.ctypes.data_as(C.POINTER(C.c_double)), n_terms, n_vec,
                               _ptr(b), _stream()))
         return b
+
+    def distribute(self, x, out, level=None):
+        level = self.n_levels - 1 if level is None else level
+        _check(lib().mfmg_distribute(self.handle, level, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def level_cells(self, level):
+        nc = self.level_info(level)["n_cells"]
+        lv = np.zeros(nc, dtype=np.int32)
+        ijk = np.zeros((nc, 3), dtype=np.int32)
+        _check(lib().mfmg_level_cells(self.handle, level, lv.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      ijk.ctypes.data_as(C.POINTER(C.c_int32))))
+        return lv, ijk
+
+    # -- learned coarse correction ------------------------------------------------
+    def net_n_params(self):
+        n = C.c_int()
+        _check(lib().mfmg_net_n_params(self.handle, C.byref(n)))
+        return n.value
+
+    def net_record(self, capacity):
+        _check(lib().mfmg_net_record(self.handle, capacity))
+
+    def net_n_recorded(self):
+        n = C.c_int()
+        _check(lib().mfmg_net_n_recorded(self.handle, C.byref(n)))
+        return n.value
+
+    def net_set_params(self, theta):
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        _check(lib().mfmg_net_set_params(self.handle, t.ctypes.data_as(C.POINTER(C.c_float)), t.size))
+
+    def net_get_params(self):
+        t = np.zeros(self.net_n_params(), dtype=np.float32)
+        _check(lib().mfmg_net_get_params(self.handle, t.ctypes.data_as(C.POINTER(C.c_float)), t.size))
+        return t
+
+    def net_loss_grad(self, X, T, grad):
+        loss = C.c_float()
+        _check(lib().mfmg_net_loss_grad(self.handle, X.shape[0], _ptr(X), _ptr(T), _ptr(grad), C.byref(loss)))
+        return loss.value
+
+    def net_train(self, epochs, batch_rows=4096, lr=1e-3, init_seed=1, shuffle_seed=2):
+        d = NetTrainDesc(epochs, batch_rows, lr, init_seed, shuffle_seed)
+        hist = (C.c_float * epochs)()
+        _check(lib().mfmg_net_train(self.handle, C.byref(d), hist))
+        return list(hist)
+
+    def net_mode(self, mode, tau=0.5):
+        _check(lib().mfmg_net_mode(self.handle, mode, tau))
+
+    def net_counts(self):
+        a, r = C.c_int(), C.c_int()
+        _check(lib().mfmg_net_counts(self.handle, C.byref(a), C.byref(r)))
+        return a.value, r.value
 
     def close(self):
         if self.handle:

@@ -225,3 +225,59 @@ def test_solve_mixed_precision(dtypes):
     err = np.linalg.norm(from_gpu(xg, P[-1]) - xo) / np.linalg.norm(xo)
     print(f"[mixed {dtypes}] {st['iterations']} it, residual {res:.2e}, err {err:.2e}")
     assert st["converged"] and res < 1.01e-10 and err < 1e-8
+
+
+@pytest.mark.parametrize("name,k", [("tiny", 2), ("small", 4), ("small_m1", 3)])
+def test_distribute(name, k):
+    """Constraint distribution: node values of every cell equal the oracle's
+    C_e x (hanging nodes interpolated, Dirichlet nodes zero)."""
+    from oracle.space import distribute_values
+    H = oracle_hierarchy(name, k)
+    S = gpu_solver(name, k)
+    P = perms(name, k)
+    Sp = H.spaces[-1]
+    x = np.random.default_rng(9).uniform(-1, 1, Sp.n_dofs)
+    lv, ijk = S.level_cells(S.n_levels - 1)
+    out = torch.empty((len(lv), (k + 1) ** 3), dtype=torch.float64, device=DEV)
+    S.distribute(to_gpu(x, P[-1]), out)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for c in range(len(lv)):
+        cell = (int(lv[c]), int(ijk[c, 0]), int(ijk[c, 1]), int(ijk[c, 2]))
+        assert np.abs(out[c] - distribute_values(Sp, cell, x)).max() < 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_discretisation_convergence_on_gpu(k):
+    """-Lap u = 3 pi^2 u, u = sin(pi x) sin(pi y) sin(pi z) on [0,1]^3: the
+    L2 error of the GPU solution (solve to 1e-12, node values from the
+    constraint distribution) decreases like h^{k+1} on meshes with hanging
+    nodes."""
+    from oracle import fe
+    from paper_2203_12292_amd import mfmg
+    nq = k + 4
+    xq, wq = fe.gauss(nq)
+    pts = np.array([(xq[a], xq[b], xq[c]) for c in range(nq) for b in range(nq) for a in range(nq)])
+    w3 = np.array([wq[a] * wq[b] * wq[c] for c in range(nq) for b in range(nq) for a in range(nq)])
+    Phi = fe.basis_at(k, pts)
+    errs = []
+    for n0 in (2, 4, 8):
+        desc = synth.ball_mesh(f"conv{n0}", n0, 0, 1, r=0.45)
+        S = mfmg.Solver(mfmg.Mesh(desc), k)
+        b = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
+        S.rhs(b, mfmg.RHS_SINE, (3 * np.pi ** 2, np.pi))
+        x = torch.zeros_like(b)
+        st = S.solve(x, b, rtol=1e-12, max_it=80)
+        assert st["converged"]
+        lv, ijk = S.level_cells(S.n_levels - 1)
+        vals = torch.empty((len(lv), (k + 1) ** 3), dtype=torch.float64, device=DEV)
+        S.distribute(x, vals)
+        vals = vals.cpu().numpy()
+        h = 1.0 / (n0 * 2.0 ** lv)
+        phys = ijk[:, None, :] * h[:, None, None] + pts[None, :, :] * h[:, None, None]
+        ue = np.prod(np.sin(np.pi * phys), axis=2)
+        uh = vals @ Phi.T
+        errs.append(np.sqrt(np.sum(h ** 3 * ((uh - ue) ** 2 @ w3))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"[conv k={k}] errors {errs} rates {rates}")
+    assert rates[-1] > k + 1 - 0.3
