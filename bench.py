@@ -10,8 +10,11 @@ scatter-add) in FP64, the paper's vmult.  ``value`` = free DoFs x steps / time
 of the timed region (inputs resident in HBM).  After the timed region the
 script solves the same problem to a relative residual of 1e-10 with the FP64
 V-cycle and with the FP32 V-cycle (FP64 CG), and reports both times; it also
-times the same-mesh plain FP64 solve, the mixed-precision variant (FP32 levels,
-bfloat16 on the two coarsest) on the 2808-cell Q2 mesh.
+times, on the 2808-cell Q2 mesh, the plain FP64 solve, the mixed-precision
+variant (FP32 levels, bfloat16 on the two coarsest) and the learned coarse
+correction (trained on the GPU on 20,000 coarse right-hand sides recorded from
+the solver); and the batch of 8 right-hand sides solved in one call with
+polynomial coarsening Q6 -> Q3 -> Q1 on the 306,536-cell sphere-shell mesh.
 
 Prints one JSON line.
 """
@@ -186,6 +189,56 @@ def main():
                 st = s1.solve(x1, b1, rtol=1e-10, max_it=100, flexible=bool(dts))
             solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                             "residual": st["final_residual"]}
+        # learned coarse correction (Q2 coarse grid, 343 DoFs)
+        s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H)
+        b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
+        x1 = torch.zeros_like(b1)
+        t0 = time.time()
+        s1.net_record(20000)
+        j = 0
+        while s1.net_n_recorded() < 20000:
+            g = synth.gaussian_rhs_training(j)
+            s1.rhs(b1, mfmg.RHS_GAUSS, g, n_terms=g.shape[0])
+            s1.solve(x1, b1, rtol=1e-10, max_it=60)
+            j += 1
+        t_rec = time.time() - t0
+        t0 = time.time()
+        hist = s1.net_train(epochs=30, batch_rows=8192, lr=2e-3, init_seed=7, shuffle_seed=11)
+        t_train = time.time() - t0
+        s1.net_record(0)
+        g = synth.gaussian_rhs_training(100000)
+        s1.rhs(b1, mfmg.RHS_GAUSS, g, n_terms=g.shape[0])
+        learned = {"pairs": 20000, "record_s": round(t_rec, 2), "train_s": round(t_train, 2),
+                   "train_loss_first_last": [hist[0], hist[-1]], "tau": 0.9}
+        for name, mode in (("exact", mfmg.COARSE_EXACT), ("learned", mfmg.COARSE_LEARNED),
+                           ("none", mfmg.COARSE_ZERO)):
+            s1.net_mode(mode, 0.9)
+            for _ in range(3):
+                if mode != mfmg.COARSE_EXACT:
+                    s1.net_counts()
+                st = s1.solve(x1, b1, rtol=1e-10, max_it=200, flexible=True)
+            rec = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"]}
+            if mode == mfmg.COARSE_LEARNED:
+                a, r, rel = s1.net_counts()
+                rec.update({"accepted": a, "rejected": r, "mean_rel_coarse_residual": rel})
+            learned[name] = rec
+        solves["cube4_q2_learned_coarse"] = learned
+        del s1
+        # p-multigrid Q6 -> Q3 -> Q1 + global coarsening, 8 right-hand sides
+        m4 = mfmg.Mesh(synth.CFG4)
+        t0 = time.time()
+        s4 = mfmg.Solver(m4, 6, mfmg.SCHEME_P_THEN_H, level_dtypes=[mfmg.F32], max_rhs=8)
+        setup4 = time.time() - t0
+        n4 = s4.n_dofs()
+        params = np.stack(synth.gaussian_rhs_batch(8))
+        b4 = torch.zeros(n4 * 8, dtype=torch.float64, device=dev)
+        s4.rhs(b4, mfmg.RHS_GAUSS, params, n_terms=4, n_vec=8)
+        x4 = torch.zeros_like(b4)
+        st = s4.solve(x4, b4, rtol=1e-10, max_it=100, flexible=True, n_vec=8)
+        solves["cube12_spheres_q6_pmg_8rhs_fp32_vcycle"] = {
+            "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
+            "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}
+        del s4
         out["time_to_solve"] = solves
 
     if not args.skip_cpu_baseline:

@@ -266,9 +266,11 @@ int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history
 /* Coarse solver of the V-cycle: MFMG_COARSE_EXACT, _LEARNED (with judge and
  * fallback, threshold tau) or _ZERO (no coarse correction; for comparison). */
 int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau);
-/* Number of learned predictions accepted / rejected since the last call
- * (resets both counters).  Synchronous. */
-int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected);
+/* Number of learned predictions accepted / rejected since the last call and
+ * the mean relative residual ||b0 - A0 y|| / ||b0|| of the predictions y
+ * (1 for no coarse correction, 0 for the exact solve); resets the counters.
+ * Synchronous.  Outputs may be NULL. */
+int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected, double* mean_rel_residual);
 
 /* ---- teardown ------------------------------------------------------------ */
 void mfmg_destroy_ctx(mfmg_ctx ctx);

@@ -457,16 +457,20 @@ int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau) {
   });
 }
 
-int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected) {
+int mfmg_net_counts(mfmg_ctx ctx, int* accepted, int* rejected, double* mean_rel_residual) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
     require_net(ctx->ctx);
     int c[2] = {0, 0};
     MFMG_HIP(hipDeviceSynchronize());
     MFMG_HIP(hipMemcpy(c, ctx->ctx.net.counters.ptr, 8, hipMemcpyDeviceToHost));
+    double rs = 0.0;
+    MFMG_HIP(hipMemcpy(&rs, ctx->ctx.net.relsum.ptr, 8, hipMemcpyDeviceToHost));
     MFMG_HIP(hipMemset(ctx->ctx.net.counters.ptr, 0, 8));
+    MFMG_HIP(hipMemset(ctx->ctx.net.relsum.ptr, 0, 8));
     if (accepted) *accepted = c[0];
     if (rejected) *rejected = c[1];
+    if (mean_rel_residual) *mean_rel_residual = (c[0] + c[1]) > 0 ? rs / (c[0] + c[1]) : 0.0;
     return MFMG_OK;
   });
 }

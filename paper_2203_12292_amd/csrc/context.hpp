@@ -48,6 +48,7 @@ struct NetState {
   DeviceArray<float> params;
   DeviceArray<double> work;
   DeviceArray<int> counters;      // accepted, rejected
+  DeviceArray<double> relsum;     // sum of ||b0 - A0 y|| / ||b0|| of the predictions
   int mode = MFMG_COARSE_EXACT;
   double tau = 0.5;
   // recording of coarse right-hand sides

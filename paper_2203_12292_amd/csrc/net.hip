@@ -197,26 +197,78 @@ __global__ void __launch_bounds__(256)
   if (lane == 0) out[static_cast<int64_t>(p) * n0 + row] = s;
 }
 
-// Coarse solve by the network with the exact solve as judge and fallback.
-// One block.  b0/x0 in storage type S.
+// Coarse solve by the network, step 1: one block of 64 threads per coarse
+// cell evaluates the MLP and adds its averaged nodal outputs to y (= work
+// + n0, zeroed beforehand); every block recomputes s = ||b0||_2.
 template <typename S>
-__global__ void __launch_bounds__(256)
-    learned_coarse_solve(int n0, int n_cells, int nq, const float* __restrict__ theta,
-                         const int32_t* __restrict__ node_dof, const float* __restrict__ inv_val,
-                         const float* __restrict__ centre, const double* __restrict__ A, const double* __restrict__ Ainv,
-                         double tau, int mode, const S* __restrict__ b, S* __restrict__ x, double* __restrict__ work,
-                         int* __restrict__ counters) {
-  __shared__ double red[256];
-  __shared__ float hbuf[2][HID];
-  double* bb = work;           // [n0]
-  double* y = work + n0;       // [n0]
-  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-    bb[i] = load_as<double>(b[i]);
-    y[i] = 0.0;
+__global__ void __launch_bounds__(64)
+    net_infer_cells(int n0, int nq, const float* __restrict__ theta, const int32_t* __restrict__ node_dof,
+                    const float* __restrict__ inv_val, const float* __restrict__ centre, const S* __restrict__ b,
+                    double* __restrict__ work) {
+  __shared__ double red[64];
+  __shared__ float xin[HID];
+  __shared__ float h1[HID];
+  __shared__ float h2[HID];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n0; i += 64) {
+    const double v = load_as<double>(b[i]);
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double nb = sqrt(red[0]);
+  if (nb == 0.0) return;
+  const float inv = static_cast<float>(1.0 / nb);
+  const int nin = nq + 3;
+  const float* W1 = theta;
+  const float* b1 = W1 + nin * HID;
+  const float* W2 = b1 + HID;
+  const float* b2 = W2 + HID * HID;
+  const float* W3 = b2 + HID;
+  const float* b3 = W3 + HID * nq;
+  if (threadIdx.x < nq) {
+    const int d = node_dof[c * nq + threadIdx.x];
+    xin[threadIdx.x] = d < 0 ? 0.0f : static_cast<float>(load_as<double>(b[d])) * inv;
+  } else if (threadIdx.x < nin) {
+    xin[threadIdx.x] = centre[3 * c + threadIdx.x - nq];
   }
   __syncthreads();
+  float acc = b1[threadIdx.x];
+  for (int q = 0; q < nin; ++q) acc += xin[q] * W1[q * HID + threadIdx.x];
+  h1[threadIdx.x] = gelu_f(acc);
+  __syncthreads();
+  acc = b2[threadIdx.x];
+  for (int k = 0; k < HID; ++k) acc += h1[k] * W2[k * HID + threadIdx.x];
+  h2[threadIdx.x] = gelu_f(acc);
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    acc = b3[threadIdx.x];
+    for (int k = 0; k < HID; ++k) acc += h2[k] * W3[k * nq + threadIdx.x];
+    const int d = node_dof[c * nq + threadIdx.x];
+    if (d >= 0) atomicAdd(&work[n0 + d], static_cast<double>(acc) * nb * inv_val[d]);
+  }
+}
+
+// Step 2 (one block): the exact coarse operator judges the prediction y; if
+// ||b0 - A0 y|| > tau ||b0|| the exact solution A0^{-1} b0 is used instead.
+// mode 2: no coarse correction (x = 0).
+template <typename S>
+__global__ void __launch_bounds__(256)
+    net_judge(int n0, const double* __restrict__ A, const double* __restrict__ Ainv, double tau, int mode,
+              const S* __restrict__ b, S* __restrict__ x, const double* __restrict__ work,
+              int* __restrict__ counters, double* __restrict__ relsum) {
+  __shared__ double red[256];
+  const double* y = work + n0;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n0; i += blockDim.x) s += bb[i] * bb[i];
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+    const double v = load_as<double>(b[i]);
+    s += v * v;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -225,53 +277,13 @@ __global__ void __launch_bounds__(256)
   }
   const double nb = sqrt(red[0]);
   __syncthreads();
-  if (nb == 0.0) {
+  if (nb == 0.0 || mode == 2) {
     for (int i = threadIdx.x; i < n0; i += blockDim.x) x[i] = store_as<S>(0.0);
     return;
   }
-  if (mode == 2) {  // no coarse correction
-    for (int i = threadIdx.x; i < n0; i += blockDim.x) x[i] = store_as<S>(0.0);
-    return;
-  }
-  const int nin = nq + 3;
-  const float* W1 = theta;
-  const float* b1 = W1 + nin * HID;
-  const float* W2 = b1 + HID;
-  const float* b2 = W2 + HID * HID;
-  const float* W3 = b2 + HID;
-  const float* b3 = W3 + HID * nq;
-  const float inv = static_cast<float>(1.0 / nb);
-  for (int c = 0; c < n_cells; ++c) {
-    // layer 1 (threads = hidden units)
-    if (threadIdx.x < HID) {
-      float acc = b1[threadIdx.x];
-      for (int q = 0; q < nq; ++q) {
-        const int d = node_dof[c * nq + q];
-        const float xin = d < 0 ? 0.0f : static_cast<float>(bb[d]) * inv;
-        acc += xin * W1[q * HID + threadIdx.x];
-      }
-      for (int t = 0; t < 3; ++t) acc += centre[3 * c + t] * W1[(nq + t) * HID + threadIdx.x];
-      hbuf[0][threadIdx.x] = gelu_f(acc);
-    }
-    __syncthreads();
-    if (threadIdx.x < HID) {
-      float acc = b2[threadIdx.x];
-      for (int k = 0; k < HID; ++k) acc += hbuf[0][k] * W2[k * HID + threadIdx.x];
-      hbuf[1][threadIdx.x] = gelu_f(acc);
-    }
-    __syncthreads();
-    if (threadIdx.x < nq) {
-      float acc = b3[threadIdx.x];
-      for (int k = 0; k < HID; ++k) acc += hbuf[1][k] * W3[k * nq + threadIdx.x];
-      const int d = node_dof[c * nq + threadIdx.x];
-      if (d >= 0) atomicAdd(&y[d], static_cast<double>(acc) * nb * inv_val[d]);
-    }
-    __syncthreads();
-  }
-  // judge: relative residual of the network's correction
   double rs = 0.0;
   for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-    double r = bb[i];
+    double r = load_as<double>(b[i]);
     for (int j = 0; j < n0; ++j) r -= A[static_cast<int64_t>(i) * n0 + j] * y[j];
     rs += r * r;
   }
@@ -281,14 +293,18 @@ __global__ void __launch_bounds__(256)
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const bool accept = sqrt(red[0]) <= tau * nb;
-  if (threadIdx.x == 0) atomicAdd(&counters[accept ? 0 : 1], 1);
+  const double rel = sqrt(red[0]) / nb;
+  const bool accept = rel <= tau;
+  if (threadIdx.x == 0) {
+    atomicAdd(&counters[accept ? 0 : 1], 1);
+    atomicAdd(relsum, rel);
+  }
   if (accept) {
     for (int i = threadIdx.x; i < n0; i += blockDim.x) x[i] = store_as<S>(y[i]);
   } else {
     for (int i = threadIdx.x; i < n0; i += blockDim.x) {
       double v = 0.0;
-      for (int j = 0; j < n0; ++j) v += Ainv[static_cast<int64_t>(i) * n0 + j] * bb[j];
+      for (int j = 0; j < n0; ++j) v += Ainv[static_cast<int64_t>(i) * n0 + j] * load_as<double>(b[j]);
       x[i] = store_as<S>(v);
     }
   }
@@ -338,6 +354,8 @@ void net_setup(Context& ctx, const LevelDofs& L0) {
   N.work.alloc(2 * static_cast<size_t>(N.n0) + 2);
   N.counters.alloc(2);
   MFMG_HIP(hipMemset(N.counters.ptr, 0, 8));
+  N.relsum.alloc(1);
+  MFMG_HIP(hipMemset(N.relsum.ptr, 0, 8));
 }
 
 void net_init_params(Context& ctx, uint64_t seed) {
@@ -457,32 +475,28 @@ void net_train(Context& ctx, const mfmg_net_train_desc& d, float* history, hipSt
   }
 }
 
-void net_coarse_solve(Context& ctx, int dtype, void* x, const void* b, hipStream_t s) {
+template <typename S>
+static void net_coarse_solve_t(Context& ctx, S* x, const S* b, hipStream_t s) {
   NetState& N = ctx.net;
   const int mode = N.mode == MFMG_COARSE_ZERO ? 2 : 1;
-  switch (dtype) {
-    case MFMG_F64:
-      learned_coarse_solve<double><<<1, 256, 0, s>>>(N.n0, N.n_cells, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
-                                                   N.centre.ptr, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode,
-                                                   static_cast<const double*>(b), static_cast<double*>(x), N.work.ptr,
-                                                   N.counters.ptr);
-      break;
-    case MFMG_F32:
-      learned_coarse_solve<float><<<1, 256, 0, s>>>(N.n0, N.n_cells, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
-                                                  N.centre.ptr, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode,
-                                                  static_cast<const float*>(b), static_cast<float*>(x), N.work.ptr,
-                                                  N.counters.ptr);
-      break;
-    case MFMG_BF16:
-      learned_coarse_solve<bf16><<<1, 256, 0, s>>>(N.n0, N.n_cells, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
-                                                 N.centre.ptr, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode,
-                                                 static_cast<const bf16*>(b), static_cast<bf16*>(x), N.work.ptr,
-                                                 N.counters.ptr);
-      break;
-    default:
-      throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  if (mode == 1) {
+    // y = work[n0 .. 2 n0) (doubles) starts at zero
+    zero_f<<<1, 256, 0, s>>>(2 * static_cast<int64_t>(N.n0), reinterpret_cast<float*>(N.work.ptr + N.n0));
+    net_infer_cells<S><<<N.n_cells, 64, 0, s>>>(N.n0, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
+                                                 N.centre.ptr, b, N.work.ptr);
   }
+  net_judge<S><<<1, 256, 0, s>>>(N.n0, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode, b, x, N.work.ptr,
+                                 N.counters.ptr, N.relsum.ptr);
   check_launch();
+}
+
+void net_coarse_solve(Context& ctx, int dtype, void* x, const void* b, hipStream_t s) {
+  switch (dtype) {
+    case MFMG_F64: net_coarse_solve_t<double>(ctx, static_cast<double*>(x), static_cast<const double*>(b), s); break;
+    case MFMG_F32: net_coarse_solve_t<float>(ctx, static_cast<float*>(x), static_cast<const float*>(b), s); break;
+    case MFMG_BF16: net_coarse_solve_t<bf16>(ctx, static_cast<bf16*>(x), static_cast<const bf16*>(b), s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
 }
 
 }  // namespace mfmg

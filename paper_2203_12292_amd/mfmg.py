@@ -88,7 +88,7 @@ _SIGS = {
     "mfmg_net_loss_grad": (_I, [_P, _I, _P, _P, _P, C.POINTER(C.c_float)]),
     "mfmg_net_train": (_I, [_P, C.POINTER(NetTrainDesc), C.POINTER(C.c_float)]),
     "mfmg_net_mode": (_I, [_P, _I, C.c_double]),
-    "mfmg_net_counts": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
+    "mfmg_net_counts": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
     "mfmg_destroy_ctx": (None, [_P]),
     "mfmg_destroy_mesh": (None, [_P]),
     "mfmg_last_error": (C.c_char_p, []),
@@ -333,9 +333,10 @@ class Solver:
         _check(lib().mfmg_net_mode(self.handle, mode, tau))
 
     def net_counts(self):
-        a, r = C.c_int(), C.c_int()
-        _check(lib().mfmg_net_counts(self.handle, C.byref(a), C.byref(r)))
-        return a.value, r.value
+        """(accepted, rejected, mean relative coarse residual of the predictions)"""
+        a, r, m = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().mfmg_net_counts(self.handle, C.byref(a), C.byref(r), C.byref(m)))
+        return a.value, r.value, m.value
 
     def close(self):
         if self.handle:

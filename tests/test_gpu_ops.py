@@ -263,7 +263,7 @@ def test_discretisation_convergence_on_gpu(k):
     errs = []
     for n0 in (2, 4, 8):
         desc = synth.ball_mesh(f"conv{n0}", n0, 0, 1, r=0.45)
-        S = mfmg.Solver(mfmg.Mesh(desc), k)
+        S = mfmg.Solver(mfmg.Mesh(desc), k, mfmg.SCHEME_H_THEN_P)
         b = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
         S.rhs(b, mfmg.RHS_SINE, (3 * np.pi ** 2, np.pi))
         x = torch.zeros_like(b)
