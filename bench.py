@@ -21,8 +21,12 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,6 +35,172 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vmult_q4_cube16_ball4_hbm_traffic.md")
+# sources that determine the operator kernels, their metadata and their compilation
+OPERATOR_SOURCES = [os.path.join("paper_2203_12292_amd", "csrc", f) for f in
+                    ("kernels.hip", "kernels.hpp", "slots.hpp", "dofs.cpp", "dofs.hpp", "fe1d.hpp", "common.hpp")]
+OPERATOR_SOURCES.append(os.path.join("paper_2203_12292_amd", "build.py"))
+
+
+def operator_source_digest():
+    h = hashlib.sha256()
+    for f in OPERATOR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per operator application from the committed counter summary,
+    or None when the operator's sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_val) or m_sha.group(1) != operator_source_digest():
+        return None
+    return float(m_val.group(1))
+
+
+def _pmc_rows(folder, counter):
+    """(kernel name, grid size, value) of every dispatch in a rocprofv3 --pmc
+    csv output folder for one counter."""
+    out = []
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.append((row["Kernel_Name"], int(row["Grid_Size"]), float(row["Counter_Value"])))
+    return out
+
+
+def _kname(name):
+    """Kernel name without return type, namespace and argument list."""
+    return name.split("(")[0].replace("void ", "").replace("mfmg::", "").strip()
+
+
+def trace_summary(trace_csv, bench_json, commands):
+    """Markdown summary of a rocprofv3 --kernel-trace run of this script: the
+    finest-level operator dispatches (largest grid of each operator kernel)
+    against the benchmark's own HIP-event average, and the top kernels."""
+    import numpy as np
+    rows = []
+    with open(trace_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            rows.append((r["Kernel_Name"], grid, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    with open(bench_json) as fh:
+        bench = json.loads(fh.read().strip().splitlines()[-1])
+
+    def finest(prefix):
+        sel = [(g, us) for name, g, us in rows if _kname(name) == prefix]
+        gmax = max(g for g, _ in sel)
+        d = [us for g, us in sel if g == gmax]
+        return gmax, len(d), float(np.mean(d))
+
+    vm = finest("vmult_batch_kernel<4, double, double>")
+    red = finest("reduce_shared_kernel<double>")
+    ev = bench["roofline"]["avg_launch_ms"] * 1e3
+    tot = {}
+    for name, _, us in rows:
+        key = _kname(name)
+        t = tot.setdefault(key, [0.0, 0])
+        t[0] += us
+        t[1] += 1
+    top = sorted(tot.items(), key=lambda kv: -kv[1][0])[:12]
+    alg = bench["roofline"]["alg_bytes_per_launch"]
+    cfg = bench["config"]
+    lines = [
+        "# Operator (vmult) on the 16^3 + 4 ball-step mesh, Q4, FP64 - kernel trace",
+        "",
+        f"Workload: {cfg['cells']} cells ({cfg['hanging_cells']} with hanging nodes), Q4,",
+        f"{cfg['free_dofs']} free DoFs.  Command (repository root on the GPU machine), then this summary:",
+        "",
+    ] + [f"    {c}" for c in commands] + [
+        "",
+        "| finest-level kernel | grid (work items) | dispatches | average |",
+        "|---|---:|---:|---:|",
+        f"| vmult_batch_kernel<4, double, double> | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
+        f"| reduce_shared_kernel<double> | {red[0]} | {red[1]} | {red[2]:.1f} us |",
+        f"| sum = one operator application | | | {vm[2] + red[2]:.1f} us |",
+        "",
+        f"The benchmark's HIP-event average over its {bench['steps']} timed steps in the same run: {ev:.1f} us",
+        f"per application ({100.0 * abs(ev - vm[2] - red[2]) / ev:.1f} % from the trace).",
+        "",
+        f"Algorithmic traffic 16 B/DoF = {alg / 1e9:.3f} GB per application -> "
+        f"{alg / ((vm[2] + red[2]) * 1e-6) / 1e9:.0f} GB/s from the trace,",
+        f"{bench['roofline']['achieved']:.0f} GB/s from the events "
+        f"({100.0 * bench['roofline']['frac']:.1f} % of 8 TB/s).",
+        "",
+        "Top kernels of the whole run (all levels, set-up and solves included):",
+        "",
+        "| total | calls | average | kernel |",
+        "|---:|---:|---:|---|",
+    ] + [f"| {t[0] / 1e3:.1f} ms | {t[1]} | {t[0] / t[1]:.1f} us | {k} |" for k, t in top]
+    return "\n".join(lines)
+
+
+def pmc_summary(fetch_dir, write_dir, n, commands):
+    """Markdown summary of the two counter passes: HBM bytes of one finest-level
+    operator application (batch kernel + shared-DoF reduction), calibrated by a
+    plain elementwise kernel that reads and writes n doubles."""
+    import numpy as np
+
+    def pick(rows, key):
+        sel = [(g, v) for name, g, v in rows if key(name)]
+        gmax = max(g for g, _ in sel)
+        return float(np.mean([v for g, v in sel if g == gmax])), sum(1 for g, _ in sel if g == gmax), gmax
+
+    res = {}
+    for label, folder, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(folder, counter)
+        res[label] = {
+            "vmult": pick(rows, lambda s: _kname(s) == "vmult_batch_kernel<4, double, double>"),
+            "reduce": pick(rows, lambda s: _kname(s) == "reduce_shared_kernel<double>"),
+            "copy": pick(rows, lambda s: "elementwise_kernel" in s),
+        }
+    f_fetch = 8.0 * n / (res["fetch"]["copy"][0] * 1024.0)
+    f_write = 8.0 * n / (res["write"]["copy"][0] * 1024.0)
+    kib = {lab: res[lab]["vmult"][0] + res[lab]["reduce"][0] for lab in ("fetch", "write")}
+    traffic = kib["fetch"] * 1024.0 * f_fetch + kib["write"] * 1024.0 * f_write
+    alg = 16.0 * n
+    lines = [
+        "# HBM traffic of one operator application, 16^3 + 4 ball-step mesh, Q4, FP64",
+        "",
+        f"{n} free DoFs.  Two counter passes of the benchmark (the finest-level",
+        "dispatches of the batch kernel and of the shared-DoF reduction are the",
+        "ones with the largest grid of their kernel), then this summary:",
+        "",
+    ] + [f"    {c}" for c in commands] + [
+        "",
+        "| kernel | grid | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |",
+        "|---|---:|---:|---:|---:|",
+    ]
+    for key, name in (("vmult", "vmult_batch_kernel<4, double, double>"), ("reduce", "reduce_shared_kernel<double>"),
+                      ("copy", "elementwise kernel y = 1.0 * x (calibration, n doubles)")):
+        fv, fd, fg = res["fetch"][key]
+        wv, _, _ = res["write"][key]
+        lines.append(f"| {name} | {fg} | {fd} | {fv:.0f} | {wv:.0f} |")
+    lines += [
+        "",
+        f"Calibration: the copy moves 8n = {8 * n} bytes each way; counter scale",
+        f"factors {f_fetch:.4f} (FETCH_SIZE) and {f_write:.4f} (WRITE_SIZE).",
+        "",
+        f"traffic_bytes_per_launch: {traffic:.0f}",
+        f"algorithmic_bytes_per_launch: {alg:.0f}",
+        f"traffic / algorithmic: {traffic / alg:.3f}",
+        f"source_sha256: {operator_source_digest()}",
+        "",
+        "The benchmark reports this traffic only while the hash of the operator",
+        "sources (kernels, metadata layout, build flags) still matches.",
+    ]
+    return "\n".join(lines)
 
 
 def _events_time(fn, k, stream):
@@ -95,10 +265,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-solves", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs and exit (no GPU)")
+    ap.add_argument("--pmc-n", type=int, default=0, help="free DoFs of the profiled run (for --pmc-summary)")
+    ap.add_argument("--pmc-command", action="append", default=[], help="command lines to quote in the summary")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="print the kernel-trace summary of a profiled run and exit (no GPU)")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary[0], args.trace_summary[1], args.pmc_command))
+        return
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_n, args.pmc_command))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
-              "operator is a design in DESIGN.md, not built.", file=sys.stderr)
+              "operator is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -136,8 +318,9 @@ def main():
     value = n * args.steps / wall
     alg_bytes = 16.0 * n  # read src + write dst, FP64 (metadata reported separately)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    # one plain copy of the same vector (calibration of the HBM byte counters)
-    y.copy_(x)
+    # a plain elementwise kernel over the same vector (calibration of the HBM byte counters)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
 
     out = {
@@ -157,7 +340,7 @@ def main():
                    "quadrature": "gauss 5^3", "hanging_cells": n_hang, "levels": solver.n_levels,
                    "setup_s": round(setup_s, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "kernel": "vmult_batch_kernel + reduce_shared_kernel (one operator application)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
     }

@@ -62,6 +62,7 @@ class Space:
         self.xi = fe.gll_points(self.k)
         self._v1d = {}
         self._rows = {}
+        self._cls = {}  # memo of classify (pure function of its arguments)
         self.cells = self.index.leaf_list()
         if build:
             self._number()
@@ -102,6 +103,14 @@ class Space:
 
     def classify(self, cell, a, b, c):
         """('dir',) | ('free', code) | ('hang', coarse_cell, (vx, vy, vz))."""
+        key = (cell, a, b, c)
+        out = self._cls.get(key)
+        if out is None:
+            out = self._classify(cell, a, b, c)
+            self._cls[key] = out
+        return out
+
+    def _classify(self, cell, a, b, c):
         abc = (a, b, c)
         if self.dirichlet and self._on_boundary(cell, abc):
             return ("dir",)

@@ -30,6 +30,9 @@ DESCS = {
     "small": synth.small_mesh(),
     "cfg1": synth.CFG1,
     "small_m1": synth.ball_mesh("small_m1", 2, 0, 2, r=0.7, centre=(-0.4, -0.3, -0.5), lo=-1.0, hi=1.0),
+    # the sphere-cut refinement of the p-multigrid workload on a 2^3 coarse grid
+    "spheres_small": synth.mesh_desc("cube2_spheres2", 2, -1.0, 1.0, 0,
+                                     [(synth.SPHERE_CUT, (0.0, 0.0, 0.0, 0.3, 0.7))] * 2),
 }
 
 SCHEME_CODES = {"h": 0, "p_then_h": 1, "h_then_p": 2}
