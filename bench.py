@@ -94,23 +94,29 @@ def trace_summary(trace_csv, bench_json, commands):
             if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
                 continue
             grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-            rows.append((r["Kernel_Name"], grid, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            rows.append((t0, _kname(r["Kernel_Name"]), grid, (t1 - t0) * 1e-3))
+    rows.sort()
     with open(bench_json) as fh:
         bench = json.loads(fh.read().strip().splitlines()[-1])
-
-    def finest(prefix):
-        sel = [(g, us) for name, g, us in rows if _kname(name) == prefix]
-        gmax = max(g for g, _ in sel)
-        d = [us for g, us in sel if g == gmax]
-        return gmax, len(d), float(np.mean(d))
-
-    vm = finest("vmult_batch_kernel<4, double, double>")
-    red = finest("reduce_shared_kernel<double>")
+    # finest-level applications: the batch-kernel dispatches with the largest
+    # grid, each paired with the shared-DoF reduction launched right after it
+    name_vm, name_red = "vmult_batch_kernel<4, double, double>", "reduce_shared_kernel<double>"
+    gmax = max(g for _, name, g, _ in rows if name == name_vm)
+    vm_t, red_t, red_g = [], [], 0
+    for q, (_, name, g, us) in enumerate(rows):
+        if name == name_vm and g == gmax:
+            vm_t.append(us)
+            if q + 1 < len(rows) and rows[q + 1][1] == name_red:
+                red_t.append(rows[q + 1][3])
+                red_g = rows[q + 1][2]
+    vm = (gmax, len(vm_t), float(np.mean(vm_t)))
+    red = (red_g, len(red_t), float(np.mean(red_t)))
+    rows = [(name, g, us) for _, name, g, us in rows]
     ev = bench["roofline"]["avg_launch_ms"] * 1e3
     tot = {}
     for name, _, us in rows:
-        key = _kname(name)
-        t = tot.setdefault(key, [0.0, 0])
+        t = tot.setdefault(name, [0.0, 0])
         t[0] += us
         t[1] += 1
     top = sorted(tot.items(), key=lambda kv: -kv[1][0])[:12]
