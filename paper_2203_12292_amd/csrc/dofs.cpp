@@ -182,29 +182,35 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   MFMG_REQUIRE(ne < (1ll << 31), MFMG_ERR_UNSUPPORTED, "too many entities");
   auto esize = [&](int64_t id) { return slot_size(ents[id].slot, k); };
 
-  // batches: consecutive cells while the touched DoFs fit the LDS budget
+  // batches: consecutive cells while the touched DoFs fit the LDS budget.  A
+  // block evaluates `quantum` cells at a time, so a full batch is cut back to
+  // a multiple of that many cells (the cut-off cells start the next batch).
   const int mcap = batch_mcap(k);
+  const int64_t quantum = BATCH_QUANTIZE ? BATCH_WAVES * cells_per_wave(k + 1) : 1;
   std::vector<int32_t> stamp(ne, -1);
   L.batch_cell_off.assign(1, 0);
   {
-    int64_t local = 0, in_batch = 0;
+    int64_t local = 0, in_batch = 0, start = 0;
     int32_t b = 0;
-    for (int64_t c = 0; c < nc; ++c) {
+    auto added = [&](int64_t c) {
       int64_t add = 0;
       for (int s = 0; s < N_SLOTS; ++s) {
         const int32_t id = L.ent_id[s * nc + c];
         if (id >= 0 && stamp[id] != b) add += esize(id);
       }
+      return add;
+    };
+    for (int64_t c = 0; c < nc; ++c) {
+      int64_t add = added(c);
       if (in_batch > 0 && (local + add > mcap || in_batch >= BATCH_MAX_CELLS)) {
+        const int64_t keep = in_batch > quantum ? in_batch / quantum * quantum : in_batch;
+        c = start + keep;
         L.batch_cell_off.push_back(static_cast<int32_t>(c));
         ++b;
+        start = c;
         local = 0;
         in_batch = 0;
-        add = 0;
-        for (int s = 0; s < N_SLOTS; ++s) {
-          const int32_t id = L.ent_id[s * nc + c];
-          if (id >= 0 && stamp[id] != b) add += esize(id);
-        }
+        add = added(c);
       }
       MFMG_REQUIRE(add <= mcap, MFMG_ERR_UNSUPPORTED, "cell exceeds the batch capacity");
       for (int s = 0; s < N_SLOTS; ++s) {
@@ -264,7 +270,7 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
 
   // batch-local layout: shared entities (first touch in the batch), then the
   // exclusive range in global order
-  L.loc.assign(static_cast<size_t>(N_SLOTS) * nc, 0xffff);
+  L.loc.assign(static_cast<size_t>(N_SLOTS) * nc, static_cast<uint16_t>(batch_mcap(k)));  // absent: zero block
   L.batch_sh_off.assign(nb + 1, 0);
   std::vector<int32_t> lstart(ne, -1);
   std::fill(stamp.begin(), stamp.end(), -1);

@@ -166,7 +166,8 @@ __device__ __forceinline__ void sym_mv(const SymMat<T, N>& A, const T (&x)[N], T
   }
 }
 
-// in-place hanging interpolation from the LDS table Hg: u <- H_s u (or H_s^T u)
+// In-place hanging interpolation of a line from the LDS table Hg (both
+// halves, [s][i][j]): u <- H_s u (H_s^T u if TRANS).
 template <int N, typename T, bool TRANS>
 __device__ __forceinline__ void interp_lds(const T* __restrict__ Hg, int s, T (&u)[N]) {
   const T* Hs = Hg + s * N * N;
@@ -394,46 +395,59 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
   }
 }
 
-// The cell pipeline with even-odd 1D operators and the hanging-node table in
-// LDS (`Hl`).  Same contract as cell_pipeline.
+// The cell pipeline with even-odd 1D operators, z-sweeps first:
+//   a = M_z u, b = K_z u;  c = M_y a, f = K_y a + M_y b;  out = h (K_x c + M_x f),
+// which is h (K_x M_y M_z + M_x K_y M_z + M_x M_y K_z) u.  Input: this lane's
+// z-line (x = ta, y = tb) of gathered values, so the z-sweeps start from
+// registers.  In a wavefront without hanging nodes the result is this lane's
+// x-line (y = ta, z = tb) and the function returns false.  Otherwise the
+// interpolations of the hanging lines (they commute with each other) are
+// applied around the sweeps: z in registers and y, x through LDS before,
+// x in registers and y, z through LDS after; the result is then this lane's
+// z-line (the gather layout) and the function returns true.  Hg (LDS) holds
+// the interpolation matrices of both halves.  Must be called by all lanes of
+// the wavefront.
 template <int K, typename T, typename Sync>
-__device__ __forceinline__ void cell_pipeline2(T* __restrict__ B0, T* __restrict__ B1, bool active, uint32_t m,
-                                               int any_hang, T h, const OpTab2<T, K + 1>& tab,
-                                               const T* __restrict__ Hl, int ta, int tb, T (&u)[K + 1]) {
+__device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, T* __restrict__ B1, uint32_t m,
+                                                     int any_hang, T h, const OpTab2<T, K + 1>& tab,
+                                                     const T* __restrict__ Hg, int ta, int tb, T (&u)[K + 1]) {
   constexpr int N = K + 1, N2 = N * N;
   const Sync sync{};
   const bool hang = mask_hanging(m);
-  if (active) {
-    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, false>(Hl, mask_sub(m, 2), u);
+  if (any_hang) {
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, false>(Hg, mask_sub(m, 2), u);
 #pragma unroll
     for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];
-  }
-  sync();
-  if (any_hang) {
-    if (active && hang && hanging_line(m, 1, ta, tb, K)) {
+    sync();
+    if (hang && hanging_line(m, 1, ta, tb, K)) {
 #pragma unroll
       for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
-      interp_lds<N, T, false>(Hl, mask_sub(m, 1), u);
+      interp_lds<N, T, false>(Hg, mask_sub(m, 1), u);
 #pragma unroll
       for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
     }
     sync();
+    if (hang && hanging_line(m, 0, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
+      interp_lds<N, T, false>(Hg, mask_sub(m, 0), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
+    }
+    sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) u[c] = B0[c * N2 + tb * N + ta];  // own z-line, rewritten below
   }
   T a[N], b[N];
-  if (active) {
+  sym_mv<N>(tab.M, u, a);
+  sym_mv<N>(tab.K, u, b);
 #pragma unroll
-    for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
-    if (hang && hanging_line(m, 0, ta, tb, K)) interp_lds<N, T, false>(Hl, mask_sub(m, 0), u);
-    sym_mv<N>(tab.M, u, a);
-    sym_mv<N>(tab.K, u, b);
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      B0[tb * N2 + ta * N + r] = a[r];
-      B1[tb * N2 + ta * N + r] = b[r];
-    }
+  for (int c = 0; c < N; ++c) {
+    B0[c * N2 + tb * N + ta] = a[c];
+    B1[c * N2 + tb * N + ta] = b[c];
   }
   sync();
-  if (active) {
+  {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       a[r] = B0[tb * N2 + r * N + ta];
@@ -450,154 +464,220 @@ __device__ __forceinline__ void cell_pipeline2(T* __restrict__ B0, T* __restrict
     }
   }
   sync();
-  if (active) {
+  {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-      a[r] = B0[r * N2 + tb * N + ta];
-      b[r] = B1[r * N2 + tb * N + ta];
+      a[r] = B0[tb * N2 + ta * N + r];
+      b[r] = B1[tb * N2 + ta * N + r];
     }
     T g1[N], g2[N];
     sym_mv<N>(tab.K, a, g1);
     sym_mv<N>(tab.M, b, g2);
 #pragma unroll
     for (int r = 0; r < N; ++r) u[r] = h * (g1[r] + g2[r]);
-    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, true>(Hl, mask_sub(m, 2), u);
-#pragma unroll
-    for (int r = 0; r < N; ++r) B0[r * N2 + tb * N + ta] = u[r];
   }
+  if (!any_hang) return false;
+  if (hang && hanging_line(m, 0, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 0), u);
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];  // this lane's own x-line
   sync();
-  if (any_hang) {
-    if (active && hang && hanging_line(m, 0, ta, tb, K)) {
-#pragma unroll
-      for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
-      interp_lds<N, T, true>(Hl, mask_sub(m, 0), u);
-#pragma unroll
-      for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
-    }
-    sync();
-  }
-  if (active) {
+  if (hang && hanging_line(m, 1, ta, tb, K)) {
 #pragma unroll
     for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
-    if (hang && hanging_line(m, 1, ta, tb, K)) interp_lds<N, T, true>(Hl, mask_sub(m, 1), u);
+    interp_lds<N, T, true>(Hg, mask_sub(m, 1), u);
+#pragma unroll
+    for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
   }
+  sync();
+#pragma unroll
+  for (int c = 0; c < N; ++c) u[c] = B0[c * N2 + tb * N + ta];
+  if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 2), u);
+  return true;
 }
 
-// Operator evaluation by cell batches.  One block per batch: the batch's
-// DoFs are loaded into LDS (shared DoFs through their index list, exclusive
-// DoFs as one contiguous range), the cells are evaluated group by group from
-// LDS and their contributions accumulated in LDS, then the exclusive DoFs are
-// stored contiguously and the shared DoFs written as this batch's partial
-// sums (reduced afterwards).  Consecutive batches run on the same XCD.
-__device__ __forceinline__ int64_t xcd_batch(int64_t bid, int64_t nb) {
-  const int64_t per = (nb + 7) / 8;
-  return (bid % 8) * per + bid / 8;
+// Per-lane constants of the operator kernel, for lane t = ta + n tb of a
+// cell: entity slot and in-entity offsets (first node, first interior node,
+// stride between interior nodes) of the lane's z-line (x = ta, y = tb) and
+// x-line (y = ta, z = tb).  Built at compile time, read once per wavefront.
+struct LaneLines {
+  uint8_t zs0, zs1, zsm, zo0, zom, zst;
+  uint8_t xs0, xs1, xsm, xo0, xom, xst;
+};
+template <int K>
+struct LaneLineTable {
+  LaneLines t[(K + 1) * (K + 1)];
+};
+template <int K>
+constexpr LaneLineTable<K> make_lane_lines() {
+  LaneLineTable<K> r{};
+  for (int tb = 0; tb <= K; ++tb)
+    for (int ta = 0; ta <= K; ++ta) {
+      LaneLines& l = r.t[ta + (K + 1) * tb];
+      l.zs0 = static_cast<uint8_t>(node_slot(ta, tb, 0, K));
+      l.zs1 = static_cast<uint8_t>(node_slot(ta, tb, K, K));
+      l.zsm = static_cast<uint8_t>(K > 1 ? node_slot(ta, tb, 1, K) : 26);
+      l.zo0 = static_cast<uint8_t>(node_offset(ta, tb, 0, K));
+      l.zom = static_cast<uint8_t>(K > 1 ? node_offset(ta, tb, 1, K) : 0);
+      l.zst = static_cast<uint8_t>(K > 2 ? node_offset(ta, tb, 2, K) - node_offset(ta, tb, 1, K) : 0);
+      l.xs0 = static_cast<uint8_t>(node_slot(0, ta, tb, K));
+      l.xs1 = static_cast<uint8_t>(node_slot(K, ta, tb, K));
+      l.xsm = static_cast<uint8_t>(K > 1 ? node_slot(1, ta, tb, K) : 26);
+      l.xo0 = static_cast<uint8_t>(node_offset(0, ta, tb, K));
+      l.xom = static_cast<uint8_t>(K > 1 ? node_offset(1, ta, tb, K) : 0);
+      l.xst = static_cast<uint8_t>(K > 2 ? node_offset(2, ta, tb, K) - node_offset(1, ta, tb, K) : 0);
+    }
+  return r;
 }
+template <int K>
+__constant__ LaneLineTable<K> kLaneLines = make_lane_lines<K>();
 
+// Operator evaluation by cell batches.  The blocks are persistent: the
+// batches are split into 8 contiguous ranges, one per XCD (block i runs on XCD
+// i mod 8), and the blocks of an XCD take the batches of its range in turn,
+// so neighbouring batches share that XCD's L2.  Per batch, the batch's DoFs
+// are loaded into LDS (shared DoFs through their index list, exclusive DoFs as
+// one contiguous range), the cells are evaluated group by group from LDS and
+// their contributions accumulated in LDS, then the exclusive DoFs are stored
+// contiguously and the shared DoFs written as this batch's partial sums
+// (reduced afterwards).  gridDim.x is a multiple of 8.
 template <int K, typename S, typename T>
 __global__ void __launch_bounds__(BATCH_WAVES * 64)
     vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
                        const int32_t* __restrict__ bsh, const int32_t* __restrict__ bex,
                        const int32_t* __restrict__ sh_idx, const int32_t* __restrict__ sh_pos, int64_t nb,
                        int64_t n_shared, double h0, OpTab2<T, K + 1> tab, const S* __restrict__ src,
-                       T* __restrict__ partial,
-                       T* __restrict__ dst, int nv) {
+                       T* __restrict__ partial, T* __restrict__ dst, int nv) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPW = cells_per_wave(N), MCAP = batch_mcap(K);
-  __shared__ T in_[MCAP];
-  __shared__ T out_[MCAP];
-  __shared__ T buf0[BATCH_WAVES * CPW * N3];
-  __shared__ T buf1[BATCH_WAVES * CPW * N3];
-  __shared__ T Hl[2 * N2];
-  const int64_t b = xcd_batch(blockIdx.x, nb);
-  if (b >= nb) return;
+  constexpr int NZ = batch_zero_entries(K), ZB = MCAP;  // zero block behind the batch's DoFs
+  constexpr int BT = BATCH_WAVES * 64, PER = (MCAP + BT - 1) / BT;
+  __shared__ T in_[MCAP + NZ];
+  __shared__ double out_[MCAP + NZ];  // contributions accumulate in FP64 (also for FP32 arithmetic)
+  __shared__ T Hg[2 * N2];
+  __shared__ T buf0[(BATCH_WAVES * CPW + 1) * N3];
+  __shared__ T buf1[(BATCH_WAVES * CPW + 1) * N3];
   const int v = blockIdx.y;
-  const int c0 = bcell[b], c1 = bcell[b + 1];
-  const int sh0 = bsh[b], nsh = bsh[b + 1] - sh0;
-  const int64_t ex0 = n_shared + bex[b];
-  const int m = nsh + (bex[b + 1] - bex[b]);
-  for (int i = threadIdx.x; i < 2 * N2; i += blockDim.x) Hl[i] = tab.Hg[i];
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const int64_t g = i < nsh ? static_cast<int64_t>(sh_idx[sh0 + i]) : ex0 + (i - nsh);
-    in_[i] = load_as<T>(src[g * nv + v]);
-    out_[i] = T(0);
-  }
+  for (int i = threadIdx.x; i < NZ; i += BT) in_[ZB + i] = T(0);
+  for (int i = threadIdx.x; i < 2 * N2; i += BT) Hg[i] = tab.Hg[i];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int lc = lane / N2;
   const int t = lane - lc * N2;
   const bool lane_used = lc < CPW;
   const int ta = t % N, tb = t / N;
-  T* B0 = buf0 + (wave * CPW + (lane_used ? lc : 0)) * N3;
-  T* B1 = buf1 + (wave * CPW + (lane_used ? lc : 0)) * N3;
-  // slots and offsets of this lane's gather line (x=ta, y=tb, z=0..k) and
-  // scatter line (x=ta, y=0..k, z=tb) do not depend on the cell
-  const int gs0 = node_slot(ta, tb, 0, K), gs1 = node_slot(ta, tb, K, K), gsm = node_slot(ta, tb, 1, K);
-  const int go0 = node_offset(ta, tb, 0, K), gom = node_offset(ta, tb, 1, K);
-  const int gst = K > 2 ? node_offset(ta, tb, 2, K) - gom : 0;
-  const int ss0 = node_slot(ta, 0, tb, K), ss1 = node_slot(ta, K, tb, K), ssm = node_slot(ta, 1, tb, K);
-  const int so0 = node_offset(ta, 0, tb, K), som = node_offset(ta, 1, tb, K);
-  const int sst = K > 2 ? node_offset(ta, 2, tb, K) - som : 0;
-  // metadata of this lane's cell, fetched one cell group ahead: the six
-  // local entity starts of its gather and scatter lines and the mask
+  // lanes without a cell work on the block's spare buffers (results unused)
+  T* B0 = buf0 + (lane_used ? wave * CPW + lc : BATCH_WAVES * CPW) * N3;
+  T* B1 = buf1 + (lane_used ? wave * CPW + lc : BATCH_WAVES * CPW) * N3;
+  const LaneLines ll = kLaneLines<K>.t[t];
+  const int gs0 = ll.zs0, gs1 = ll.zs1, gsm = ll.zsm, go0 = ll.zo0, gom = ll.zom, gst = ll.zst;
+  const int ss0 = ll.xs0, ss1 = ll.xs1, ssm = ll.xsm, so0 = ll.xo0, som = ll.xom, sst = ll.xst;
   struct Pre {
     int g0, g1, gm, s0, s1, sm;
     uint32_t mask;
   };
-  auto fetch = [&](int64_t cell) {
-    Pre p{0xffff, 0xffff, 0xffff, 0xffff, 0xffff, 0xffff, 0u};
-    if (lane_used && cell < c1) {
-      const uint16_t* L = meta[cell].loc;
-      p.g0 = L[gs0];
-      p.g1 = L[gs1];
-      p.gm = L[gsm];
-      p.s0 = L[ss0];
-      p.s1 = L[ss1];
-      p.sm = L[ssm];
-      p.mask = meta[cell].mask;
-    }
-    return p;
-  };
-  int cw = c0 + wave * CPW;
-  Pre nx = fetch(cw + lc);
-  __syncthreads();
-  for (; cw < c1; cw += BATCH_WAVES * CPW) {
-    const int64_t cell = cw + lc;
-    const bool active = lane_used && cell < c1;
-    const Pre cur = nx;
-    nx = fetch(cw + BATCH_WAVES * CPW + lc);
-    const uint32_t mk = active ? cur.mask : 0u;
-    const int wave_hang = __any(mask_hanging(mk) ? 1 : 0);
-    const T h = static_cast<T>(ldexp(h0, -mask_level(mk)));
-    T u[N];
-    if (active) {
-      u[0] = cur.g0 == 0xffff ? T(0) : in_[cur.g0 + go0];
-      u[K] = cur.g1 == 0xffff ? T(0) : in_[cur.g1 + go0];
-      if constexpr (K > 1) {
+
+  const int64_t per = (nb + 7) / 8;
+  const int64_t lo = (blockIdx.x % 8) * per;
+  const int64_t hi = lo + per < nb ? lo + per : nb;
+  const int64_t stride = gridDim.x / 8;
+  for (int64_t b = lo + blockIdx.x / 8; b < hi; b += stride) {
+    const int c0 = bcell[b], c1 = bcell[b + 1];
+    const int sh0 = bsh[b], nsh = bsh[b + 1] - sh0;
+    const int64_t ex0 = n_shared + bex[b];
+    const int m = nsh + (bex[b + 1] - bex[b]);
+    // stage the batch's DoFs: all index loads of a thread, then all value
+    // loads, then the LDS stores, so that the loads of a thread overlap
+    {
+      int64_t gi[PER];
 #pragma unroll
-        for (int c = 1; c < K; ++c) u[c] = cur.gm == 0xffff ? T(0) : in_[cur.gm + gom + (c - 1) * gst];
+      for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * BT;
+        gi[q] = i < nsh ? static_cast<int64_t>(sh_idx[sh0 + i]) : ex0 + (i - nsh);
       }
-    }
-    cell_pipeline2<K, T, WaveSync>(B0, B1, active, mk, wave_hang, h, tab, Hl, ta, tb, u);
-    if (active) {
-      if (cur.s0 != 0xffff) atomicAdd(&out_[cur.s0 + so0], u[0]);
-      if (cur.s1 != 0xffff) atomicAdd(&out_[cur.s1 + so0], u[K]);
-      if constexpr (K > 1) {
-        if (cur.sm != 0xffff) {
-          if (ssm == 26) {
+      T val[PER];
 #pragma unroll
-            for (int r = 1; r < K; ++r) out_[cur.sm + som + (r - 1) * sst] = u[r];
-          } else {
+      for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * BT;
+        val[q] = i < m ? load_as<T>(src[gi[q] * nv + v]) : T(0);
+      }
 #pragma unroll
-            for (int r = 1; r < K; ++r) atomicAdd(&out_[cur.sm + som + (r - 1) * sst], u[r]);
-          }
+      for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * BT;
+        if (i < m) {
+          in_[i] = val[q];
+          out_[i] = 0.0;
         }
       }
     }
-    WaveSync{}();  // the next cell group reuses this wavefront's buffers
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    if (i < nsh) partial[static_cast<int64_t>(sh_pos[sh0 + i]) * nv + v] = out_[i];
-    else dst[(ex0 + (i - nsh)) * nv + v] = out_[i];
+    // metadata of this lane's cell, fetched one cell group ahead: the six
+    // local entity starts of its z-line and x-line and the mask (the loads are
+    // unconditional, from the batch's first cell for lanes without a cell, so
+    // that the wait for them can be counted exactly; such lanes then point at
+    // the zero block)
+    auto fetch = [&](int64_t cell) {
+      const bool ok = lane_used && cell < c1;
+      const CellMeta* M = meta + (ok ? cell : c0);
+      const uint16_t* L = M->loc;
+      Pre p{L[gs0], L[gs1], L[gsm], L[ss0], L[ss1], L[ssm], M->mask};
+      p.g0 = ok ? p.g0 : ZB;
+      p.g1 = ok ? p.g1 : ZB;
+      p.gm = ok ? p.gm : ZB;
+      p.s0 = ok ? p.s0 : ZB;
+      p.s1 = ok ? p.s1 : ZB;
+      p.sm = ok ? p.sm : ZB;
+      p.mask = ok ? p.mask : 0u;
+      return p;
+    };
+    int cw = c0 + wave * CPW;
+    Pre nx = fetch(cw + lc);
+    __syncthreads();
+    for (; cw < c1; cw += BATCH_WAVES * CPW) {
+      const Pre cur = nx;
+      nx = fetch(cw + BATCH_WAVES * CPW + lc);
+      const uint32_t mk = cur.mask;
+      const int wave_hang = __any(mask_hanging(mk) ? 1 : 0);
+      const T h = static_cast<T>(ldexp(h0, -mask_level(mk)));
+      T u[N];
+      u[0] = in_[cur.g0 + go0];
+      u[K] = in_[cur.g1 + go0];
+      if constexpr (K > 1) {
+#pragma unroll
+        for (int c = 1; c < K; ++c) u[c] = in_[cur.gm + gom + (c - 1) * gst];
+      }
+      const bool zline = cell_pipeline_zfirst<K, T, WaveSync>(B0, B1, mk, wave_hang, h, tab, Hg, ta, tb, u);
+      // scatter-add along the result line, skipping absent entities and
+      // lanes without a cell (they point at the zero block); a line through
+      // the cell interior (slot 26) holds DoFs of this cell only
+      const int s0 = zline ? cur.g0 : cur.s0, s1 = zline ? cur.g1 : cur.s1, sm = zline ? cur.gm : cur.sm;
+      const int o0 = zline ? go0 : so0, om = zline ? gom : som, st = zline ? gst : sst;
+      if (s0 < ZB) atomicAdd(&out_[s0 + o0], static_cast<double>(u[0]));
+      if (s1 < ZB) atomicAdd(&out_[s1 + o0], static_cast<double>(u[K]));
+      if constexpr (K > 1) {
+        if (sm < ZB) {
+          if ((zline ? gsm : ssm) == 26) {
+#pragma unroll
+            for (int r = 1; r < K; ++r) out_[sm + om + (r - 1) * st] = static_cast<double>(u[r]);
+          } else {
+#pragma unroll
+            for (int r = 1; r < K; ++r) atomicAdd(&out_[sm + om + (r - 1) * st], static_cast<double>(u[r]));
+          }
+        }
+      }
+      WaveSync{}();  // the next cell group reuses this wavefront's buffers
+    }
+    // write back: partial sums of the shared DoFs, exclusive DoFs in place
+    int32_t pos[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = threadIdx.x + q * BT;
+      pos[q] = i < nsh ? sh_pos[sh0 + i] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = threadIdx.x + q * BT;
+      if (i < nsh) partial[static_cast<int64_t>(pos[q]) * nv + v] = static_cast<T>(out_[i]);
+      else if (i < m) dst[(ex0 + (i - nsh)) * nv + v] = static_cast<T>(out_[i]);
+    }
+    __syncthreads();  // the next batch overwrites in_ and out_
   }
 }
 
@@ -1167,8 +1247,23 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
   constexpr int N = K + 1;
   if (c.n_cells == 0) return;
   static const OpTab2<T, N> tab = make_optab2<T, N>();
+  // persistent blocks: as many as are resident on the device at once (a
+  // multiple of 8, one share per XCD), at most one per batch
+  static const int64_t resident = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T>), BATCH_WAVES * 64, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return int64_t(0);
+    }
+    return static_cast<int64_t>(cus) * per_cu * BATCH_GRID_FACTOR;
+  }();
   const int64_t nb = c.n_batches;
-  dim3 grid(static_cast<unsigned>(8 * ((nb + 7) / 8)), nv);
+  int64_t blocks = 8 * ((nb + 7) / 8);
+  if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
+  dim3 grid(static_cast<unsigned>(blocks), nv);
   vmult_batch_kernel<K, S, T><<<grid, BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, c.sh_pos, nb, c.n_shared, c.h0, tab,
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv);

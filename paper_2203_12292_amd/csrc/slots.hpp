@@ -66,18 +66,34 @@ constexpr int BATCH_WAVES = MFMG_BATCH_WAVES;
 __host__ __device__ constexpr int cells_per_wave(int n) { return 64 / (n * n); }
 
 // Cell batches of the operator: a batch's DoFs are staged in LDS (input and
-// accumulated output, FP64) next to the per-wave work buffers, within
-// BATCH_LDS_BYTES per block.  batch_mcap(k) bounds the DoFs a batch touches.
+// accumulated output) next to the per-wave work buffers, within
+// BATCH_LDS_BYTES per block (sized for FP64).  batch_mcap(k) bounds the DoFs a
+// batch touches.  Behind them sits a block of batch_zero_entries(k) entries:
+// zeros in the input and a discarded area in the output, where absent
+// (Dirichlet) entities and lanes without a cell point, so that gather and
+// scatter need no branches.
 #ifndef MFMG_BATCH_LDS_BYTES
 #define MFMG_BATCH_LDS_BYTES 81920
 #endif
 constexpr int BATCH_LDS_BYTES = MFMG_BATCH_LDS_BYTES;
 constexpr int BATCH_MAX_CELLS = 1024;
+#ifndef MFMG_BATCH_QUANTIZE
+#define MFMG_BATCH_QUANTIZE 1
+#endif
+constexpr bool BATCH_QUANTIZE = MFMG_BATCH_QUANTIZE != 0;
+// persistent operator blocks per resident block slot of the device
+#ifndef MFMG_BATCH_GRID_FACTOR
+#define MFMG_BATCH_GRID_FACTOR 2
+#endif
+constexpr int BATCH_GRID_FACTOR = MFMG_BATCH_GRID_FACTOR;
+__host__ __device__ constexpr int batch_zero_entries(int k) { return k > 1 ? (k - 1) * (k - 1) * (k - 1) : 1; }
 __host__ __device__ constexpr int batch_work_bytes(int k) {
-  return BATCH_WAVES * cells_per_wave(k + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8;
+  // two n^3 buffers per cell of every wavefront plus one spare pair for lanes
+  // without a cell, and the hanging-interpolation matrices of both halves
+  return (BATCH_WAVES * cells_per_wave(k + 1) + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8 + 2 * (k + 1) * (k + 1) * 8;
 }
 __host__ __device__ constexpr int batch_mcap(int k) {
-  return ((BATCH_LDS_BYTES - batch_work_bytes(k)) / 16) / 64 * 64;
+  return ((BATCH_LDS_BYTES - batch_work_bytes(k)) / 16 - batch_zero_entries(k)) / 64 * 64;
 }
 
 // Mask bits.
