@@ -66,16 +66,17 @@ def recorded_traffic():
 
 
 def _pmc_rows(folder, counter):
-    """(kernel name, grid size, value) of every dispatch in a rocprofv3 --pmc
-    csv output folder for one counter."""
+    """(dispatch id, kernel name, grid size, value) of every dispatch in a
+    rocprofv3 --pmc csv output folder for one counter, in dispatch order."""
     out = []
     for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
         with open(path, newline="") as fh:
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                out.append((row["Kernel_Name"], int(row["Grid_Size"]), float(row["Counter_Value"])))
-    return out
+                out.append((int(row["Dispatch_Id"]), _kname(row["Kernel_Name"]), int(row["Grid_Size"]),
+                            float(row["Counter_Value"])))
+    return sorted(out)
 
 
 def _kname(name):
@@ -99,19 +100,16 @@ def trace_summary(trace_csv, bench_json, commands):
     rows.sort()
     with open(bench_json) as fh:
         bench = json.loads(fh.read().strip().splitlines()[-1])
-    # finest-level applications: the batch-kernel dispatches with the largest
-    # grid, each paired with the shared-DoF reduction launched right after it
+    # finest-level applications: each batch-kernel dispatch followed by its
+    # shared-DoF reduction; the finest level is the pair whose reduction has
+    # the largest grid (the reduction is sized by the level's shared DoFs)
     name_vm, name_red = "vmult_batch_kernel<4, double, double>", "reduce_shared_kernel<double>"
-    gmax = max(g for _, name, g, _ in rows if name == name_vm)
-    vm_t, red_t, red_g = [], [], 0
-    for q, (_, name, g, us) in enumerate(rows):
-        if name == name_vm and g == gmax:
-            vm_t.append(us)
-            if q + 1 < len(rows) and rows[q + 1][1] == name_red:
-                red_t.append(rows[q + 1][3])
-                red_g = rows[q + 1][2]
-    vm = (gmax, len(vm_t), float(np.mean(vm_t)))
-    red = (red_g, len(red_t), float(np.mean(red_t)))
+    pairs = [(rows[q][2], rows[q + 1][2], rows[q][3], rows[q + 1][3]) for q in range(len(rows) - 1)
+             if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
+    red_g = max(p[1] for p in pairs)
+    sel = [p for p in pairs if p[1] == red_g]
+    vm = (sel[0][0], len(sel), float(np.mean([p[2] for p in sel])))
+    red = (red_g, len(sel), float(np.mean([p[3] for p in sel])))
     rows = [(name, g, us) for _, name, g, us in rows]
     ev = bench["roofline"]["avg_launch_ms"] * 1e3
     tot = {}
@@ -158,19 +156,25 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
     plain elementwise kernel that reads and writes n doubles."""
     import numpy as np
 
-    def pick(rows, key):
-        sel = [(g, v) for name, g, v in rows if key(name)]
-        gmax = max(g for g, _ in sel)
-        return float(np.mean([v for g, v in sel if g == gmax])), sum(1 for g, _ in sel if g == gmax), gmax
+    def pick(rows):
+        """(mean value, dispatches, grid) of the finest-level batch kernel, of
+        its reduction (pairs whose reduction has the largest grid) and of the
+        calibration copy (elementwise kernel with the largest grid)."""
+        name_vm, name_red = "vmult_batch_kernel<4, double, double>", "reduce_shared_kernel<double>"
+        pairs = [(rows[q], rows[q + 1]) for q in range(len(rows) - 1)
+                 if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
+        red_g = max(b[2] for _, b in pairs)
+        sel = [(a, b) for a, b in pairs if b[2] == red_g]
+        cp = [r for r in rows if "elementwise_kernel" in r[1]]
+        cp_g = max(r[2] for r in cp)
+        cp = [r for r in cp if r[2] == cp_g]
+        return {"vmult": (float(np.mean([a[3] for a, _ in sel])), len(sel), sel[0][0][2]),
+                "reduce": (float(np.mean([b[3] for _, b in sel])), len(sel), red_g),
+                "copy": (float(np.mean([r[3] for r in cp])), len(cp), cp_g)}
 
     res = {}
     for label, folder, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
-        rows = _pmc_rows(folder, counter)
-        res[label] = {
-            "vmult": pick(rows, lambda s: _kname(s) == "vmult_batch_kernel<4, double, double>"),
-            "reduce": pick(rows, lambda s: _kname(s) == "reduce_shared_kernel<double>"),
-            "copy": pick(rows, lambda s: "elementwise_kernel" in s),
-        }
+        res[label] = pick(_pmc_rows(folder, counter))
     f_fetch = 8.0 * n / (res["fetch"]["copy"][0] * 1024.0)
     f_write = 8.0 * n / (res["write"]["copy"][0] * 1024.0)
     kib = {lab: res[lab]["vmult"][0] + res[lab]["reduce"][0] for lab in ("fetch", "write")}
@@ -180,8 +184,8 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         "# HBM traffic of one operator application, 16^3 + 4 ball-step mesh, Q4, FP64",
         "",
         f"{n} free DoFs.  Two counter passes of the benchmark (the finest-level",
-        "dispatches of the batch kernel and of the shared-DoF reduction are the",
-        "ones with the largest grid of their kernel), then this summary:",
+        "applications are the (batch kernel, shared-DoF reduction) dispatch",
+        "pairs whose reduction has the largest grid), then this summary:",
         "",
     ] + [f"    {c}" for c in commands] + [
         "",

@@ -555,7 +555,6 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
   __shared__ T Hg[2 * N2];
   __shared__ T buf0[(BATCH_WAVES * CPW + 1) * N3];
   __shared__ T buf1[(BATCH_WAVES * CPW + 1) * N3];
-  const int v = blockIdx.y;
   for (int i = threadIdx.x; i < NZ; i += BT) in_[ZB + i] = T(0);
   for (int i = threadIdx.x; i < 2 * N2; i += BT) Hg[i] = tab.Hg[i];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -578,7 +577,14 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
   const int64_t lo = (blockIdx.x % 8) * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
   const int64_t stride = gridDim.x / 8;
-  for (int64_t b = lo + blockIdx.x / 8; b < hi; b += stride) {
+  // several vectors: one after the other within each batch, so that the
+  // interleaved values of a DoF come from cache after the first (one loop
+  // over (batch, vector) pairs keeps the batch's values out of registers
+  // across the vectors)
+  for (int64_t w = 0;; ++w) {
+    const int64_t b = lo + blockIdx.x / 8 + (w / nv) * stride;
+    if (b >= hi) break;
+    const int v = static_cast<int>(w % nv);
     const int c0 = bcell[b], c1 = bcell[b + 1];
     const int sh0 = bsh[b], nsh = bsh[b + 1] - sh0;
     const int64_t ex0 = n_shared + bex[b];
@@ -677,7 +683,7 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       if (i < nsh) partial[static_cast<int64_t>(pos[q]) * nv + v] = static_cast<T>(out_[i]);
       else if (i < m) dst[(ex0 + (i - nsh)) * nv + v] = static_cast<T>(out_[i]);
     }
-    __syncthreads();  // the next batch overwrites in_ and out_
+    __syncthreads();  // the next batch or vector overwrites in_ and out_
   }
 }
 
@@ -964,9 +970,12 @@ __global__ void __launch_bounds__(TR_THREADS)
   __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
   __shared__ T Y3[IDENT ? 1 : NF3];
   const int64_t g = blockIdx.x;
-  const int v = blockIdx.y;
   const int64_t cc = group_coarse[g];
   const uint32_t mc = cmask[cc];
+  // the vectors one after the other in the same block: the interleaved
+  // values of a DoF share cache lines
+  for (int v = 0; v < nv; ++v) {
+  if (v > 0) __syncthreads();
   for (int i = threadIdx.x; i < NC3; i += blockDim.x) {
     const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
     const int s = node_slot(a, b, c, KC);
@@ -1000,6 +1009,7 @@ __global__ void __launch_bounds__(TR_THREADS)
     const int64_t idx = static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v;
     add_to<S, T>(&dst[idx], Y[i] / static_cast<T>(val), val == 1);
   }
+  }
 }
 
 template <int KF, int KC, int NF, typename S, typename T>
@@ -1016,9 +1026,12 @@ __global__ void __launch_bounds__(TR_THREADS)
   __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
   __shared__ T Y3[IDENT ? 1 : NF3];
   const int64_t g = blockIdx.x;
-  const int v = blockIdx.y;
   const int64_t cc = group_coarse[g];
   const uint32_t mc = cmask[cc];
+  // the vectors one after the other in the same block: the interleaved
+  // values of a DoF share cache lines
+  for (int v = 0; v < nv; ++v) {
+  if (v > 0) __syncthreads();
   T* Yw = IDENT ? X : Y3;
   for (int i = threadIdx.x; i < NF3; i += blockDim.x) {
     const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
@@ -1053,6 +1066,7 @@ __global__ void __launch_bounds__(TR_THREADS)
     const int32_t e = cent[s * ncc + cc];
     if (e < 0) continue;
     add_to<S, T>(&dst[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v], X[i], s == 26);
+  }
   }
 }
 
@@ -1165,22 +1179,34 @@ __global__ void __launch_bounds__(256)
 // ---- FP64 reductions and CG updates ----------------------------------------
 constexpr int DOT_BLOCKS = 512;
 
+// per-vector partial dot products of interleaved vectors ([n][nv], nv <= 8):
+// each thread accumulates all components of its DoFs, so that a block reads
+// contiguous memory
 __global__ void __launch_bounds__(256)
     dot_stage1(int64_t n_dofs, int nv, const double* __restrict__ a, const double* __restrict__ b,
                double* __restrict__ partial) {
-  __shared__ double red[256];
-  const int v = blockIdx.y;
-  double s = 0.0;
+  __shared__ double red[8][256];
+  double s[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) s[v] = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_dofs;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s += a[i * nv + v] * b[i * nv + v];
-  red[threadIdx.x] = s;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      if (v < nv) s[v] += a[i * nv + v] * b[i * nv + v];
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) red[v][threadIdx.x] = s[v];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        if (v < nv) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[v * DOT_BLOCKS + blockIdx.x] = red[0];
+  if (threadIdx.x < nv) partial[threadIdx.x * DOT_BLOCKS + blockIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ void __launch_bounds__(256) dot_stage2(int nv, const double* __restrict__ partial,
@@ -1263,8 +1289,7 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
   const int64_t nb = c.n_batches;
   int64_t blocks = 8 * ((nb + 7) / 8);
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
-  dim3 grid(static_cast<unsigned>(blocks), nv);
-  vmult_batch_kernel<K, S, T><<<grid, BATCH_WAVES * 64, 0, s>>>(
+  vmult_batch_kernel<K, S, T><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, c.sh_pos, nb, c.n_shared, c.h0, tab,
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv);
   check_launch();
@@ -1337,7 +1362,7 @@ void transfer_launch(bool prolong, const CellView& f, const CellView& c, const T
   using T = typename Acc<S>::type;
   if (ng == 0) return;
   static const TrTab<T, NF, KC + 1> tab = make_trtab<T, NF, KC + 1>(KF, KC);
-  dim3 grid(static_cast<unsigned>(ng), nv);
+  dim3 grid(static_cast<unsigned>(ng));
   if (prolong)
     prolongate_kernel<KF, KC, NF, S, T><<<grid, TR_THREADS, 0, s>>>(
         f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc, gf, ng, nchild, t.valence, tab,
@@ -1608,7 +1633,8 @@ int dot_partials_needed() { return DOT_BLOCKS; }
 
 void launch_dot(int64_t n_dofs, int nv, const double* a, const double* b, double* partial, double* result,
                 hipStream_t s) {
-  dot_stage1<<<dim3(DOT_BLOCKS, nv), 256, 0, s>>>(n_dofs, nv, a, b, partial);
+  if (nv < 1 || nv > 8) throw Error(MFMG_ERR_INVALID_ARG, "dot: n_vec must be in [1, 8]");
+  dot_stage1<<<DOT_BLOCKS, 256, 0, s>>>(n_dofs, nv, a, b, partial);
   check_launch();
   dot_stage2<<<nv, 256, 0, s>>>(nv, partial, result);
   check_launch();
