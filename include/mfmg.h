@@ -87,7 +87,13 @@ enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2 };
 typedef struct {
   int degree;            /* finest degree k, 1 <= k <= 6 */
   int scheme;            /* MFMG_SCHEME_* */
-  int dirichlet;         /* 1: homogeneous Dirichlet on the whole boundary */
+  int dirichlet;         /* 1: homogeneous Dirichlet on the whole boundary;
+                            0: none (pure Neumann): the operator is singular
+                            (constants are its null space), so only the
+                            level calls (vmult, diagonal, smooth, residual,
+                            transfers, rhs, distribute) are available and
+                            coarse_solve, vcycle and solve return
+                            MFMG_ERR_UNSUPPORTED */
   int n_level_dtype;     /* entries used in level_dtype (0: all MFMG_F64) */
   int level_dtype[MFMG_MAX_LEVELS]; /* storage type of V-cycle level vectors,
                                        index 0 = coarsest; missing = last entry */
@@ -189,7 +195,11 @@ int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* 
                       const void* src_fine, void* stream);
 
 /* [async] x = A^(0)^{-1} b on the coarsest level (exact: dense inverse from a
- * host Cholesky factorisation of the assembled coarse matrix). */
+ * host Cholesky factorisation of the assembled coarse matrix).
+ *
+ * Every vector argument of the level calls may be NULL when its level has no
+ * free DoF (for example one Q1 cell with Dirichlet boundary); such a call
+ * does nothing. */
 int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b, void* stream);
 
 /* [async] Algorithm 1: copy b (FP64) to the finest level in that level's

@@ -43,6 +43,16 @@ void check_ptr(const void* p, const char* name) {
   MFMG_REQUIRE(p != nullptr, MFMG_ERR_INVALID_ARG, std::string("null pointer: ") + name);
 }
 
+// a vector of n entries: NULL is accepted only when it is empty
+void check_vec(const void* p, int64_t n, const char* name) {
+  MFMG_REQUIRE(p != nullptr || n == 0, MFMG_ERR_INVALID_ARG, std::string("null pointer: ") + name);
+}
+
+void require_dirichlet(mfmg::Context& c) {
+  MFMG_REQUIRE(c.desc.dirichlet != 0, MFMG_ERR_UNSUPPORTED,
+               "the pure Neumann operator is singular: no coarse solve, V-cycle or solve");
+}
+
 void check_nv(mfmg::Context& c, int nv) {
   MFMG_REQUIRE(nv >= 1 && nv <= 8, MFMG_ERR_INVALID_ARG, "n_vec must be in [1, 8]");
   (void)c;
@@ -180,13 +190,14 @@ int mfmg_smoother_range(mfmg_ctx ctx, int level, double* lambda_min, double* lam
 int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(dst, "dst");
-    check_ptr(src, "src");
     check_dtype(dtype);
     check_nv(ctx->ctx, n_vec);
-    MFMG_REQUIRE(dst != src, MFMG_ERR_INVALID_ARG, "dst and src must not alias");
     mfmg::Level& L = ctx->ctx.level(level);
     MFMG_REQUIRE(n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+    check_vec(dst, L.n_dofs, "dst");
+    check_vec(src, L.n_dofs, "src");
+    if (L.n_dofs == 0) return MFMG_OK;
+    MFMG_REQUIRE(dst != src, MFMG_ERR_INVALID_ARG, "dst and src must not alias");
     if (dtype == MFMG_BF16) {
       mfmg::launch_vmult(L.view, dtype, n_vec, L.t.ptr, src, as_stream(stream));
       mfmg::launch_acc_to_storage(dtype, L.n_dofs * n_vec, L.t.ptr, dst, as_stream(stream));
@@ -200,9 +211,10 @@ int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const v
 int mfmg_diagonal(mfmg_ctx ctx, int level, int dtype, void* diag, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(diag, "diag");
     check_dtype(dtype);
     mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(diag, L.n_dofs, "diag");
+    if (L.n_dofs == 0) return MFMG_OK;
     if (dtype == MFMG_F64) {
       mfmg::launch_diagonal(L.view, static_cast<double*>(diag), as_stream(stream));
     } else {
@@ -217,18 +229,19 @@ int mfmg_smooth(mfmg_ctx ctx, int level, int dtype, int n_vec, void* x, const vo
                 const double* lambda, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(x, "x");
-    check_ptr(b, "b");
     check_dtype(dtype);
     mfmg::Level& L = ctx->ctx.level(level);
     MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
     MFMG_REQUIRE(dtype == L.dtype, MFMG_ERR_INVALID_ARG, "dtype must equal the level's storage type");
+    check_vec(x, L.n_dofs, "x");
+    check_vec(b, L.n_dofs, "b");
     double lmin = L.lmin, lmax = L.lmax;
     if (lambda) {
       lmin = lambda[0];
       lmax = lambda[1];
       MFMG_REQUIRE(lmax > lmin && lmin > 0, MFMG_ERR_INVALID_ARG, "need 0 < lambda_min < lambda_max");
     }
+    if (L.n_dofs == 0) return MFMG_OK;
     mfmg::level_smooth(ctx->ctx, level, n_vec, x, b, x_is_zero != 0, lmin, lmax, as_stream(stream));
     return MFMG_OK;
   });
@@ -238,13 +251,14 @@ int mfmg_residual(mfmg_ctx ctx, int level, int dtype, int n_vec, void* r, const 
                   void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(r, "r");
-    check_ptr(b, "b");
-    check_ptr(x, "x");
     check_dtype(dtype);
     mfmg::Level& L = ctx->ctx.level(level);
     MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
     MFMG_REQUIRE(dtype == L.dtype, MFMG_ERR_INVALID_ARG, "dtype must equal the level's storage type");
+    check_vec(r, L.n_dofs, "r");
+    check_vec(b, L.n_dofs, "b");
+    check_vec(x, L.n_dofs, "x");
+    if (L.n_dofs == 0) return MFMG_OK;
     mfmg::level_residual(ctx->ctx, level, n_vec, r, b, x, as_stream(stream));
     return MFMG_OK;
   });
@@ -254,10 +268,13 @@ int mfmg_prolongate_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void
                         void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(dst_fine, "dst_fine");
-    check_ptr(src_coarse, "src_coarse");
     check_dtype(dtype);
     check_nv(ctx->ctx, n_vec);
+    MFMG_REQUIRE(fine_level >= 1, MFMG_ERR_INVALID_ARG, "fine level");
+    const int64_t nf = ctx->ctx.level(fine_level).n_dofs, nc = ctx->ctx.level(fine_level - 1).n_dofs;
+    check_vec(dst_fine, nf, "dst_fine");
+    check_vec(src_coarse, nc, "src_coarse");
+    if (nf == 0 || nc == 0) return MFMG_OK;
     mfmg::level_prolongate_add(ctx->ctx, fine_level, dtype, n_vec, dst_fine, src_coarse, as_stream(stream));
     return MFMG_OK;
   });
@@ -267,10 +284,13 @@ int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* 
                       void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(dst_coarse, "dst_coarse");
-    check_ptr(src_fine, "src_fine");
     check_dtype(dtype);
     check_nv(ctx->ctx, n_vec);
+    MFMG_REQUIRE(fine_level >= 1, MFMG_ERR_INVALID_ARG, "fine level");
+    const int64_t nf = ctx->ctx.level(fine_level).n_dofs, nc = ctx->ctx.level(fine_level - 1).n_dofs;
+    check_vec(src_fine, nf, "src_fine");
+    check_vec(dst_coarse, nc, "dst_coarse");
+    if (nf == 0 || nc == 0) return MFMG_OK;
     mfmg::level_restrict_add(ctx->ctx, fine_level, dtype, n_vec, dst_coarse, src_fine, as_stream(stream));
     return MFMG_OK;
   });
@@ -279,10 +299,12 @@ int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* 
 int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(x, "x");
-    check_ptr(b, "b");
     check_dtype(dtype);
     check_nv(ctx->ctx, n_vec);
+    require_dirichlet(ctx->ctx);
+    check_vec(x, ctx->ctx.n0, "x");
+    check_vec(b, ctx->ctx.n0, "b");
+    if (ctx->ctx.n0 == 0) return MFMG_OK;
     mfmg::coarse_solve(ctx->ctx, dtype, n_vec, x, b, as_stream(stream));
     return MFMG_OK;
   });
@@ -291,8 +313,10 @@ int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b
 int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(x_f64, "x");
-    check_ptr(b_f64, "b");
+    require_dirichlet(ctx->ctx);
+    check_vec(x_f64, ctx->ctx.fine().n_dofs, "x");
+    check_vec(b_f64, ctx->ctx.fine().n_dofs, "b");
+    if (ctx->ctx.fine().n_dofs == 0) return MFMG_OK;
     mfmg::vcycle(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64),
                  as_stream(stream));
     return MFMG_OK;
@@ -303,9 +327,17 @@ int mfmg_solve(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, double r
                mfmg_solve_stats* stats, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(x_f64, "x");
-    check_ptr(b_f64, "b");
+    require_dirichlet(ctx->ctx);
+    check_vec(x_f64, ctx->ctx.fine().n_dofs, "x");
+    check_vec(b_f64, ctx->ctx.fine().n_dofs, "b");
     MFMG_REQUIRE(rtol > 0 && max_it >= 0, MFMG_ERR_INVALID_ARG, "rtol must be > 0, max_it >= 0");
+    if (ctx->ctx.fine().n_dofs == 0) {
+      if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->converged = 1;
+      }
+      return static_cast<int>(MFMG_OK);
+    }
     int st = mfmg::pcg(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64), rtol,
                        max_it, flexible != 0, stats, as_stream(stream));
     if (st == MFMG_ERR_NOT_CONVERGED) g_last_error = "PCG did not converge within max_it";
@@ -318,13 +350,14 @@ int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_term
              void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(b_f64, "b");
     check_ptr(params, "params");
     check_nv(ctx->ctx, n_vec);
     MFMG_REQUIRE(kind == MFMG_RHS_CONST || kind == MFMG_RHS_GAUSS || kind == MFMG_RHS_SINE, MFMG_ERR_INVALID_ARG,
                  "rhs kind");
     MFMG_REQUIRE(kind != MFMG_RHS_GAUSS || n_terms >= 1, MFMG_ERR_INVALID_ARG, "n_terms");
     mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(b_f64, L.n_dofs, "b");
+    if (L.n_dofs == 0) return MFMG_OK;
     const size_t np = kind == MFMG_RHS_CONST ? 1 : kind == MFMG_RHS_SINE ? 2 : static_cast<size_t>(n_terms) * 5 * n_vec;
     mfmg::DeviceArray<double> dp;
     dp.upload(params, np);
@@ -338,9 +371,9 @@ int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_term
 int mfmg_distribute(mfmg_ctx ctx, int level, const void* x_f64, void* out_f64, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");
-    check_ptr(x_f64, "x");
     check_ptr(out_f64, "out");
     mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(x_f64, L.n_dofs, "x");
     mfmg::launch_distribute(L.view, static_cast<const double*>(x_f64), static_cast<double*>(out_f64),
                             as_stream(stream));
     return MFMG_OK;

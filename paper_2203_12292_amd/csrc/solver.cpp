@@ -301,16 +301,18 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   {
     Level& L0 = ctx.levels[0];
     ctx.n0 = L0.n_dofs;
-    MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
-    std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k));
-    ctx.coarse_A64.upload(A);
-    std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
-    std::vector<float> inv32(inv.begin(), inv.end());
-    ctx.coarse_inv64.upload(inv);
-    ctx.coarse_inv32.upload(inv32);
+    if (desc.dirichlet) {  // (the pure Neumann coarse matrix is singular)
+      MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
+      std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k));
+      ctx.coarse_A64.upload(A);
+      std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
+      std::vector<float> inv32(inv.begin(), inv.end());
+      ctx.coarse_inv64.upload(inv);
+      ctx.coarse_inv32.upload(inv32);
+    }
   }
   // learned coarse correction (available for small coarse levels without hanging nodes)
-  if (ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0) net_setup(ctx, host[0]);
+  if (desc.dirichlet && ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0) net_setup(ctx, host[0]);
   // PCG work space
   const int64_t nf = ctx.fine().n_dofs * ctx.max_rhs;
   ctx.cg_r.alloc(nf);

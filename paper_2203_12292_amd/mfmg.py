@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libmfmg.so")
 MFMG_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: "NOT_CONVERGED",
           -6: "BREAKDOWN", -7: "NET_REJECTED"}
+(ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN,
+ ERR_NET_REJECTED) = -1, -2, -3, -4, -5, -6, -7
 F64, F32, BF16 = 0, 1, 2
 SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P = 0, 1, 2
 RHS_CONST, RHS_GAUSS, RHS_SINE = 0, 1, 2

@@ -135,3 +135,23 @@ def test_rhs_and_solve_full_size_q6_eight_rhs():
     res = (torch.linalg.norm(b - r, dim=0) / torch.linalg.norm(b, dim=0)).cpu().numpy()
     print(f"[solve] {st['iterations']} it, recomputed residuals {res.max():.2e}", flush=True)
     assert st["converged"] and res.max() < 1.05e-10 and 3 <= st["iterations"] <= 40
+
+
+def test_neumann_constants_full_size_q4():
+    """Without Dirichlet conditions the constants span the null space of the
+    constrained operator: A 1 = 0 at all 67.8M DoFs, through every hanging
+    face and edge of the mesh (a property that needs no oracle at this size)."""
+    from paper_2203_12292_amd import mfmg
+    print("[setup] cube16_ball4_q4 pure Neumann", flush=True)
+    S = mfmg.Solver(mfmg.Mesh(synth.CFG2), 4, mfmg.SCHEME_H_THEN_P, dirichlet=False)
+    fine = S.n_levels - 1
+    one = torch.ones(S.n_dofs(fine), dtype=torch.float64, device=DEV)
+    y = torch.empty_like(one)
+    d = torch.empty_like(one)
+    S.vmult(fine, y, one)
+    S.diagonal(fine, d)
+    torch.cuda.synchronize()
+    ratio = float(y.abs().max()) / float(d.abs().max())
+    print(f"[neumann] {one.numel()} DoFs: max |A 1| / max diag = {ratio:.2e}", flush=True)
+    assert ratio <= 1e-12 and float(d.min()) > 0.0
+    S.close()
