@@ -225,6 +225,30 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   const int64_t nb = static_cast<int64_t>(L.batch_cell_off.size()) - 1;
   L.n_batches = nb;
 
+  // within each batch, cells with hanging nodes first: the operator evaluates
+  // several cells per wavefront, and a wavefront takes the hanging-node path
+  // if any of its cells needs it
+  {
+    std::vector<int64_t> order(nc);
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t w = L.batch_cell_off[b];
+      for (int pass = 0; pass < 2; ++pass)
+        for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
+          if (mask_hanging(L.mask[c]) == (pass == 0)) order[w++] = c;
+    }
+    std::vector<Cell> cells2(nc);
+    std::vector<uint32_t> mask2(nc);
+    std::vector<int32_t> ent2(L.ent_id.size());
+    for (int64_t c = 0; c < nc; ++c) {
+      cells2[c] = L.cells[order[c]];
+      mask2[c] = L.mask[order[c]];
+      for (int s = 0; s < N_SLOTS; ++s) ent2[s * nc + c] = L.ent_id[s * nc + order[c]];
+    }
+    L.cells.swap(cells2);
+    L.mask.swap(mask2);
+    L.ent_id.swap(ent2);
+  }
+
   // shared (touched by >= 2 batches) or exclusive
   std::vector<int32_t> n_touch(ne, 0);
   std::fill(stamp.begin(), stamp.end(), -1);
@@ -335,31 +359,32 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
   std::vector<int64_t> group_start(ncc + 1, 0);
   std::vector<int32_t> group_cells;
   group_cells.reserve(nf);
+  // lookup of fine cells by (level, key): the two levels order their cells
+  // independently (by batches), also on equal meshes
+  std::vector<std::pair<uint64_t, int32_t>> idx(nf);
+  for (int64_t c = 0; c < nf; ++c) {
+    const Cell& x = fine.cells[c];
+    idx[c] = {(static_cast<uint64_t>(x.level) << 59) ^ cell_key(x.i, x.j, x.k), static_cast<int32_t>(c)};
+  }
+  std::sort(idx.begin(), idx.end());
+  auto find = [&](int l, int64_t i, int64_t j, int64_t k) -> int32_t {
+    uint64_t key = (static_cast<uint64_t>(l) << 59) ^ cell_key(i, j, k);
+    auto it = std::lower_bound(idx.begin(), idx.end(), std::make_pair(key, static_cast<int32_t>(-1)));
+    if (it != idx.end() && it->first == key) return it->second;
+    return -1;
+  };
   if (polynomial) {
     MFMG_REQUIRE(nf == ncc, MFMG_ERR_INVALID_ARG, "polynomial transfer needs equal meshes");
     for (int64_t c = 0; c < ncc; ++c) {
-      const Cell &a = fine.cells[c], &b = coarse.cells[c];
-      MFMG_REQUIRE(a.level == b.level && a.i == b.i && a.j == b.j && a.k == b.k, MFMG_ERR_INVALID_ARG,
-                   "polynomial transfer needs equal meshes");
+      const Cell& x = coarse.cells[c];
+      const int32_t f = find(x.level, x.i, x.j, x.k);
+      MFMG_REQUIRE(f >= 0, MFMG_ERR_INVALID_ARG, "polynomial transfer needs equal meshes");
       T.ident_coarse.push_back(static_cast<int32_t>(c));
-      T.ident_fine.push_back(static_cast<int32_t>(c));
-      group_cells.push_back(static_cast<int32_t>(c));
+      T.ident_fine.push_back(f);
+      group_cells.push_back(f);
       group_start[c + 1] = group_start[c] + 1;
     }
   } else {
-    // lookup of fine cells by (level, key)
-    std::vector<std::pair<uint64_t, int32_t>> idx(nf);
-    for (int64_t c = 0; c < nf; ++c) {
-      const Cell& x = fine.cells[c];
-      idx[c] = {(static_cast<uint64_t>(x.level) << 59) ^ cell_key(x.i, x.j, x.k), static_cast<int32_t>(c)};
-    }
-    std::sort(idx.begin(), idx.end());
-    auto find = [&](int l, int64_t i, int64_t j, int64_t k) -> int32_t {
-      uint64_t key = (static_cast<uint64_t>(l) << 59) ^ cell_key(i, j, k);
-      auto it = std::lower_bound(idx.begin(), idx.end(), std::make_pair(key, static_cast<int32_t>(-1)));
-      if (it != idx.end() && it->first == key) return it->second;
-      return -1;
-    };
     for (int64_t c = 0; c < ncc; ++c) {
       const Cell& x = coarse.cells[c];
       int32_t f = find(x.level, x.i, x.j, x.k);
