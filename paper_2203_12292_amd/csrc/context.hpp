@@ -25,7 +25,7 @@ struct Level {
   std::vector<int32_t> host_levels, host_ijk;  // cell order of the level
   DeviceArray<uint32_t> mask;
   DeviceArray<CellMeta> meta;
-  DeviceArray<int32_t> batch_cell, batch_sh, batch_ex, sh_idx, sh_pos, red_off;
+  DeviceArray<int32_t> batch_cell, batch_sh, batch_ex, sh_idx, red_off, red_idx;
   DeviceArray<char> partial;
   CellView view;
   DeviceArray<double> diag;

@@ -324,10 +324,12 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   L.red_off.assign(L.n_shared + 1, 0);
   for (int32_t g : L.sh_idx) ++L.red_off[g + 1];
   for (int64_t i = 0; i < L.n_shared; ++i) L.red_off[i + 1] += L.red_off[i];
-  L.sh_pos.assign(L.sh_idx.size(), 0);
+  // partial sums are stored batch by batch (position p = batch-local shared
+  // entry); red_idx lists, for each shared DoF in CSR order, its positions
+  L.red_idx.assign(L.sh_idx.size(), 0);
   {
     std::vector<int32_t> fill(L.red_off.begin(), L.red_off.end() - 1);
-    for (size_t p = 0; p < L.sh_idx.size(); ++p) L.sh_pos[p] = fill[L.sh_idx[p]]++;
+    for (size_t p = 0; p < L.sh_idx.size(); ++p) L.red_idx[fill[L.sh_idx[p]]++] = static_cast<int32_t>(p);
   }
   for (size_t e = 0; e < ents.size(); ++e) ents[e].first_dof = static_cast<int32_t>(start[e]);
 

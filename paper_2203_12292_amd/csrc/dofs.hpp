@@ -16,10 +16,11 @@
 // DoFs forming one contiguous range.  A batch's local vector lists its shared
 // DoFs (explicit global indices) followed by its exclusive ones (a contiguous
 // copy of the global range).  Cells address it with 16-bit local entity
-// starts.  Shared DoFs receive one partial sum per touching batch; the
-// partial sums of shared DoF s occupy positions red_off[s] .. red_off[s+1]-1
-// of a partial buffer (`sh_pos` gives the position of each local shared DoF),
-// summed by a second pass.
+// starts.  Shared DoFs receive one partial sum per touching batch, written
+// batch by batch into a partial buffer (position = the batch's offset in the
+// local shared lists plus the local index); the positions of shared DoF s are
+// red_idx[red_off[s] .. red_off[s+1]-1], summed in that order by a second
+// pass.
 //
 // Gather maps with hanging-node constraints (Section 3.2: constraints applied
 // while the DoF values are set up, via an updated DoF map and in-place 1D
@@ -72,8 +73,8 @@ struct LevelDofs {
   std::vector<int32_t> batch_ex_off;    // [n_batches+1] exclusive DoFs start at n_shared + batch_ex_off[b]
   std::vector<int32_t> sh_idx;          // global DoF of each local shared DoF
   std::vector<uint16_t> loc;            // [N_SLOTS][n_cells] local entity start, 0xffff Dirichlet
-  std::vector<int32_t> sh_pos;          // partial-buffer position of each local shared DoF
-  std::vector<int32_t> red_off;         // [n_shared+1]
+  std::vector<int32_t> red_off;         // [n_shared+1] CSR over the shared DoFs
+  std::vector<int32_t> red_idx;         // partial-buffer positions (batch order) of each shared DoF
   bool slot_hanging(int64_t c, int s) const;
 };
 

@@ -544,7 +544,7 @@ template <int K, typename S, typename T>
 __global__ void __launch_bounds__(BATCH_WAVES * 64)
     vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
                        const int32_t* __restrict__ bsh, const int32_t* __restrict__ bex,
-                       const int32_t* __restrict__ sh_idx, const int32_t* __restrict__ sh_pos, int64_t nb,
+                       const int32_t* __restrict__ sh_idx, int64_t nb,
                        int64_t n_shared, double h0, OpTab2<T, K + 1> tab, const S* __restrict__ src,
                        T* __restrict__ partial, T* __restrict__ dst, int nv) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPW = cells_per_wave(N), MCAP = batch_mcap(K);
@@ -669,35 +669,33 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       }
       WaveSync{}();  // the next cell group reuses this wavefront's buffers
     }
-    // write back: partial sums of the shared DoFs, exclusive DoFs in place
-    int32_t pos[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int i = threadIdx.x + q * BT;
-      pos[q] = i < nsh ? sh_pos[sh0 + i] : 0;
-    }
+    // write back: the partial sums of the shared DoFs as one contiguous range
+    // (the batch's part of the partial buffer), exclusive DoFs in place
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = threadIdx.x + q * BT;
-      if (i < nsh) partial[static_cast<int64_t>(pos[q]) * nv + v] = static_cast<T>(out_[i]);
+      if (i < nsh) partial[static_cast<int64_t>(sh0 + i) * nv + v] = static_cast<T>(out_[i]);
       else if (i < m) dst[(ex0 + (i - nsh)) * nv + v] = static_cast<T>(out_[i]);
     }
     __syncthreads();  // the next batch or vector overwrites in_ and out_
   }
 }
 
-// dst[s] = sum of the partial sums of shared DoF s (fixed order)
+// dst[s] = sum of the partial sums of shared DoF s, in the fixed order of its
+// batches (red_idx holds their positions in the batch-ordered partial buffer)
 template <typename T>
 __global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __restrict__ red_off,
-                                     const T* __restrict__ partial, T* __restrict__ dst) {
+                                     const int32_t* __restrict__ red_idx, const T* __restrict__ partial,
+                                     T* __restrict__ dst) {
   const int64_t n = n_shared * nv;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t sd = i / nv;
     const int v = static_cast<int>(i - sd * nv);
     T acc = T(0);
-    for (int j = red_off[sd]; j < red_off[sd + 1]; ++j) acc += partial[static_cast<int64_t>(j) * nv + v];
+    for (int j = red_off[sd]; j < red_off[sd + 1]; ++j)
+      acc += partial[static_cast<int64_t>(red_idx[j]) * nv + v];
     dst[i] = acc;
   }
 }
@@ -1290,12 +1288,12 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
   int64_t blocks = 8 * ((nb + 7) / 8);
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
   vmult_batch_kernel<K, S, T><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
-      c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, c.sh_pos, nb, c.n_shared, c.h0, tab,
+      c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv);
   check_launch();
   if (c.n_shared > 0) {
     reduce_shared_kernel<T><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
-        c.n_shared, nv, c.red_off, static_cast<const T*>(c.partial), static_cast<T*>(dst));
+        c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst));
     check_launch();
   }
 }

@@ -34,7 +34,7 @@ struct CellView {
   const int32_t* batch_sh = nullptr;
   const int32_t* batch_ex = nullptr;
   const int32_t* sh_idx = nullptr;
-  const int32_t* sh_pos = nullptr;
+  const int32_t* red_idx = nullptr;
   const int32_t* red_off = nullptr;
   void* partial = nullptr;            // scratch: partial sums, (sh_idx size) x max_rhs x 8 bytes
 };

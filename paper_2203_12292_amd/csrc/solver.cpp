@@ -250,7 +250,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     L.batch_sh.upload(H.batch_sh_off);
     L.batch_ex.upload(H.batch_ex_off);
     L.sh_idx.upload(H.sh_idx);
-    L.sh_pos.upload(H.sh_pos);
+    L.red_idx.upload(H.red_idx);
     L.red_off.upload(H.red_off);
     L.partial.alloc(std::max<size_t>(1, H.sh_idx.size()) * ctx.max_rhs * 8);
     L.view.n_batches = H.n_batches;
@@ -259,7 +259,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     L.view.batch_sh = L.batch_sh.ptr;
     L.view.batch_ex = L.batch_ex.ptr;
     L.view.sh_idx = L.sh_idx.ptr;
-    L.view.sh_pos = L.sh_pos.ptr;
+    L.view.red_idx = L.red_idx.ptr;
     L.view.red_off = L.red_off.ptr;
     L.view.partial = L.partial.ptr;
     const int64_t nrhs = L.n_dofs * ctx.max_rhs;
