@@ -292,23 +292,30 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
       L.ent[s * nc + c] = id < 0 ? -1 : static_cast<int32_t>(start[id]);
     }
 
-  // batch-local layout: shared entities (first touch in the batch), then the
-  // exclusive range in global order
+  // batch-local layout: shared entities in global order (so that every
+  // batch's partial sums, and with them the reduction's reads, follow the
+  // global order of the shared DoFs), then the exclusive range in global order
   L.loc.assign(static_cast<size_t>(N_SLOTS) * nc, static_cast<uint16_t>(batch_mcap(k)));  // absent: zero block
   L.batch_sh_off.assign(nb + 1, 0);
   std::vector<int32_t> lstart(ne, -1);
   std::fill(stamp.begin(), stamp.end(), -1);
+  std::vector<int32_t> bshared;
   for (int64_t b = 0; b < nb; ++b) {
-    int64_t nsh = 0;
+    bshared.clear();
     for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
       for (int s = 0; s < N_SLOTS; ++s) {
         const int32_t id = L.ent_id[s * nc + c];
         if (id < 0 || n_touch[id] < 2 || stamp[id] == static_cast<int32_t>(b)) continue;
         stamp[id] = static_cast<int32_t>(b);
-        lstart[id] = static_cast<int32_t>(nsh);
-        for (int t = 0; t < esize(id); ++t) L.sh_idx.push_back(static_cast<int32_t>(start[id] + t));
-        nsh += esize(id);
+        bshared.push_back(id);
       }
+    std::sort(bshared.begin(), bshared.end(), [&](int32_t a, int32_t c) { return start[a] < start[c]; });
+    int64_t nsh = 0;
+    for (int32_t id : bshared) {
+      lstart[id] = static_cast<int32_t>(nsh);
+      for (int t = 0; t < esize(id); ++t) L.sh_idx.push_back(static_cast<int32_t>(start[id] + t));
+      nsh += esize(id);
+    }
     L.batch_sh_off[b + 1] = static_cast<int32_t>(L.batch_sh_off[b] + nsh);
     const int64_t ex_global = L.n_shared + L.batch_ex_off[b];
     for (int64_t c = L.batch_cell_off[b]; c < L.batch_cell_off[b + 1]; ++c)
