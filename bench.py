@@ -103,7 +103,7 @@ def trace_summary(trace_csv, bench_json, commands):
     # finest-level applications: each batch-kernel dispatch followed by its
     # shared-DoF reduction; the finest level is the pair whose reduction has
     # the largest grid (the reduction is sized by the level's shared DoFs)
-    name_vm, name_red = "vmult_batch_kernel<4, double, double>", "reduce_shared_kernel<double>"
+    name_vm, name_red = "vmult_batch_kernel<4, double, double, 0>", "reduce_shared_kernel<double, double, 0>"
     pairs = [(rows[q][2], rows[q + 1][2], rows[q][3], rows[q + 1][3]) for q in range(len(rows) - 1)
              if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
     red_g = max(p[1] for p in pairs)
@@ -130,8 +130,8 @@ def trace_summary(trace_csv, bench_json, commands):
         "",
         "| finest-level kernel | grid (work items) | dispatches | average |",
         "|---|---:|---:|---:|",
-        f"| vmult_batch_kernel<4, double, double> | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
-        f"| reduce_shared_kernel<double> | {red[0]} | {red[1]} | {red[2]:.1f} us |",
+        f"| vmult_batch_kernel<4, double, double, 0> | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
+        f"| reduce_shared_kernel<double, double, 0> | {red[0]} | {red[1]} | {red[2]:.1f} us |",
         f"| sum = one operator application | | | {vm[2] + red[2]:.1f} us |",
         "",
         f"The benchmark's HIP-event average over its {bench['steps']} timed steps in the same run: {ev:.1f} us",
@@ -160,7 +160,7 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         """(mean value, dispatches, grid) of the finest-level batch kernel, of
         its reduction (pairs whose reduction has the largest grid) and of the
         calibration copy (elementwise kernel with the largest grid)."""
-        name_vm, name_red = "vmult_batch_kernel<4, double, double>", "reduce_shared_kernel<double>"
+        name_vm, name_red = "vmult_batch_kernel<4, double, double, 0>", "reduce_shared_kernel<double, double, 0>"
         pairs = [(rows[q], rows[q + 1]) for q in range(len(rows) - 1)
                  if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
         red_g = max(b[2] for _, b in pairs)
@@ -192,7 +192,7 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         "| kernel | grid | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |",
         "|---|---:|---:|---:|---:|",
     ]
-    for key, name in (("vmult", "vmult_batch_kernel<4, double, double>"), ("reduce", "reduce_shared_kernel<double>"),
+    for key, name in (("vmult", "vmult_batch_kernel<4, double, double, 0>"), ("reduce", "reduce_shared_kernel<double, double, 0>"),
                       ("copy", "elementwise kernel y = 1.0 * x (calibration, n doubles)")):
         fv, fd, fg = res["fetch"][key]
         wv, _, _ = res["write"][key]

@@ -531,6 +531,25 @@ constexpr LaneLineTable<K> make_lane_lines() {
 template <int K>
 __constant__ LaneLineTable<K> kLaneLines = make_lane_lines<K>();
 
+// Final value t = (A x) of DoF g, vector v, and the fused step applied to it
+template <typename S, typename T, int FK>
+__device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv, int v, T t, T* __restrict__ dst) {
+  const int64_t e = g * nv + v;
+  if constexpr (FK == FUSE_NONE) {
+    dst[e] = t;
+  } else if constexpr (FK == FUSE_RESIDUAL) {
+    static_cast<S*>(f.r)[e] = store_as<S>(load_as<T>(static_cast<const S*>(f.b)[e]) - t);
+  } else {
+    S* d = static_cast<S*>(f.d);
+    S* x = static_cast<S*>(f.x);
+    const T di = static_cast<const T*>(f.dinv)[g];
+    const T dd = f.c_dd != 0.0 ? static_cast<T>(f.c_dd) * load_as<T>(d[e]) : T(0);
+    const T dn = dd + static_cast<T>(f.c_r) * di * (load_as<T>(static_cast<const S*>(f.b)[e]) - t);
+    x[e] = store_as<S>(load_as<T>(x[e]) + dn);
+    d[e] = store_as<S>(dn);
+  }
+}
+
 // Operator evaluation by cell batches.  The blocks are persistent: the
 // batches are split into 8 contiguous ranges, one per XCD (block i runs on XCD
 // i mod 8), and the blocks of an XCD take the batches of its range in turn,
@@ -540,13 +559,21 @@ __constant__ LaneLineTable<K> kLaneLines = make_lane_lines<K>();
 // their contributions accumulated in LDS, then the exclusive DoFs are stored
 // contiguously and the shared DoFs written as this batch's partial sums
 // (reduced afterwards).  gridDim.x is a multiple of 8.
-template <int K, typename S, typename T>
-__global__ void __launch_bounds__(BATCH_WAVES * 64)
+// register budget: the fused variants up to degree 4 are held to 4
+// wavefronts per SIMD (two blocks per CU, as the LDS allows); elsewhere the
+// compiler's own allocation is kept
+template <int K, int FK>
+struct BatchWavesPerEu {
+  static constexpr int value = (FK != FUSE_NONE && K <= 4) ? 4 : 1;
+};
+
+template <int K, typename S, typename T, int FK>
+__global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BatchWavesPerEu<K, FK>::value)))
     vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
                        const int32_t* __restrict__ bsh, const int32_t* __restrict__ bex,
                        const int32_t* __restrict__ sh_idx, int64_t nb,
                        int64_t n_shared, double h0, OpTab2<T, K + 1> tab, const S* __restrict__ src,
-                       T* __restrict__ partial, T* __restrict__ dst, int nv) {
+                       T* __restrict__ partial, T* __restrict__ dst, int nv, FusedStep fs) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPW = cells_per_wave(N), MCAP = batch_mcap(K);
   constexpr int NZ = batch_zero_entries(K), ZB = MCAP;  // zero block behind the batch's DoFs
   constexpr int BT = BATCH_WAVES * 64, PER = (MCAP + BT - 1) / BT;
@@ -676,18 +703,19 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
     for (int q = 0; q < PER; ++q) {
       const int i = threadIdx.x + q * BT;
       if (i < nsh) partial[static_cast<int64_t>(sh0 + i) * nv + v] = static_cast<T>(out_[i]);
-      else if (i < m) dst[(ex0 + (i - nsh)) * nv + v] = static_cast<T>(out_[i]);
+      else if (i < m) finish_dof<S, T, FK>(fs, ex0 + (i - nsh), nv, v, static_cast<T>(out_[i]), dst);
     }
     __syncthreads();  // the next batch or vector overwrites in_ and out_
   }
 }
 
-// dst[s] = sum of the partial sums of shared DoF s, in the fixed order of its
-// batches (red_idx holds their positions in the batch-ordered partial buffer)
-template <typename T>
+// (A x)_s = sum of the partial sums of shared DoF s, in the fixed order of its
+// batches (red_idx holds their positions in the batch-ordered partial
+// buffer), then the fused step
+template <typename S, typename T, int FK>
 __global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __restrict__ red_off,
                                      const int32_t* __restrict__ red_idx, const T* __restrict__ partial,
-                                     T* __restrict__ dst) {
+                                     T* __restrict__ dst, FusedStep fs) {
   const int64_t n = n_shared * nv;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -696,7 +724,7 @@ __global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __
     T acc = T(0);
     for (int j = red_off[sd]; j < red_off[sd + 1]; ++j)
       acc += partial[static_cast<int64_t>(red_idx[j]) * nv + v];
-    dst[i] = acc;
+    finish_dof<S, T, FK>(fs, sd, nv, v, acc, dst);
   }
 }
 
@@ -1106,7 +1134,7 @@ __global__ void cheb_kernel(int64_t n_dofs, int nv, int first, typename Acc<S>::
       dn = c_r * di * load_as<A>(b[i]);
       x[i] = store_as<S>(dn);
     } else {
-      dn = c_dd * load_as<A>(d[i]) + c_r * di * (load_as<A>(b[i]) - t[i]);
+      dn = (c_dd != A(0) ? c_dd * load_as<A>(d[i]) : A(0)) + c_r * di * (load_as<A>(b[i]) - t[i]);
       x[i] = store_as<S>(load_as<A>(x[i]) + dn);
     }
     d[i] = store_as<S>(dn);
@@ -1265,8 +1293,8 @@ void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
   check_launch();
 }
 
-template <int K, typename S>
-void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t s) {
+template <int K, typename S, int FK>
+void vmult_k(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
   using T = typename Acc<S>::type;
   constexpr int N = K + 1;
   if (c.n_cells == 0) return;
@@ -1278,7 +1306,7 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T>), BATCH_WAVES * 64, 0) != hipSuccess) {
+            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T, FK>), BATCH_WAVES * 64, 0) != hipSuccess) {
       (void)hipGetLastError();
       return int64_t(0);
     }
@@ -1287,26 +1315,36 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, hipStream_t 
   const int64_t nb = c.n_batches;
   int64_t blocks = 8 * ((nb + 7) / 8);
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
-  vmult_batch_kernel<K, S, T><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
+  vmult_batch_kernel<K, S, T, FK><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
-      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv);
+      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f);
   check_launch();
   if (c.n_shared > 0) {
-    reduce_shared_kernel<T><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
-        c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst));
+    reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
+        c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
     check_launch();
   }
 }
 
+template <int K, typename S>
+void vmult_kf(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+  switch (f.kind) {
+    case FUSE_NONE: vmult_k<K, S, FUSE_NONE>(c, nv, dst, src, f, s); break;
+    case FUSE_CHEB: vmult_k<K, S, FUSE_CHEB>(c, nv, dst, src, f, s); break;
+    case FUSE_RESIDUAL: vmult_k<K, S, FUSE_RESIDUAL>(c, nv, dst, src, f, s); break;
+    default: throw Error(MFMG_ERR_INVALID_ARG, "fused step");
+  }
+}
+
 template <typename S>
-void vmult_s(const CellView& c, int nv, void* dst, const void* src, hipStream_t s) {
+void vmult_s(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
   switch (c.k) {
-    case 1: vmult_k<1, S>(c, nv, dst, src, s); break;
-    case 2: vmult_k<2, S>(c, nv, dst, src, s); break;
-    case 3: vmult_k<3, S>(c, nv, dst, src, s); break;
-    case 4: vmult_k<4, S>(c, nv, dst, src, s); break;
-    case 5: vmult_k<5, S>(c, nv, dst, src, s); break;
-    case 6: vmult_k<6, S>(c, nv, dst, src, s); break;
+    case 1: vmult_kf<1, S>(c, nv, dst, src, f, s); break;
+    case 2: vmult_kf<2, S>(c, nv, dst, src, f, s); break;
+    case 3: vmult_kf<3, S>(c, nv, dst, src, f, s); break;
+    case 4: vmult_kf<4, S>(c, nv, dst, src, f, s); break;
+    case 5: vmult_kf<5, S>(c, nv, dst, src, f, s); break;
+    case 6: vmult_kf<6, S>(c, nv, dst, src, f, s); break;
     default: throw Error(MFMG_ERR_UNSUPPORTED, "degree");
   }
 }
@@ -1416,13 +1454,18 @@ void transfer_s(bool prolong, const CellView& f, const CellView& c, const Transf
 
 }  // namespace
 
-void launch_vmult(const CellView& c, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
+void launch_vmult_fused(const CellView& c, int dtype, int nv, void* dst, const void* src, const FusedStep& f,
+                        hipStream_t s) {
   switch (dtype) {
-    case MFMG_F64: vmult_s<double>(c, nv, dst, src, s); break;
-    case MFMG_F32: vmult_s<float>(c, nv, dst, src, s); break;
-    case MFMG_BF16: vmult_s<bf16>(c, nv, dst, src, s); break;
+    case MFMG_F64: vmult_s<double>(c, nv, dst, src, f, s); break;
+    case MFMG_F32: vmult_s<float>(c, nv, dst, src, f, s); break;
+    case MFMG_BF16: vmult_s<bf16>(c, nv, dst, src, f, s); break;
     default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
   }
+}
+
+void launch_vmult(const CellView& c, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
+  launch_vmult_fused(c, dtype, nv, dst, src, FusedStep{}, s);
 }
 
 void launch_diagonal(const CellView& c, double* diag, hipStream_t s) {

@@ -39,6 +39,22 @@ struct CellView {
   void* partial = nullptr;            // scratch: partial sums, (sh_idx size) x max_rhs x 8 bytes
 };
 
+// An elementwise step fused into the operator's output: for every DoF i and
+// vector v, with t = (A x)_i: none (dst = t), Chebyshev (Saad, Alg. 12.1:
+// d = c_dd d + c_r D^{-1} (b - t), x += d; x is the operator's input, updated
+// in place once no batch reads it any more) or residual (r = b - t).  b, x,
+// d and r are in the storage type, dinv in the arithmetic type.
+enum { FUSE_NONE = 0, FUSE_CHEB = 1, FUSE_RESIDUAL = 2 };
+struct FusedStep {
+  int kind = FUSE_NONE;
+  const void* b = nullptr;
+  const void* dinv = nullptr;
+  void* d = nullptr;
+  void* x = nullptr;
+  void* r = nullptr;
+  double c_dd = 0.0, c_r = 0.0;
+};
+
 struct TransferView {
   bool polynomial = false;
   const int32_t* ident_coarse = nullptr;
@@ -55,6 +71,10 @@ struct TransferView {
 
 // dst_acc = A src (every entry written; no initialisation needed)
 void launch_vmult(const CellView& c, int dtype, int nv, void* dst_acc, const void* src, hipStream_t s);
+// operator application with a fused elementwise step on its output (dst_acc
+// unused unless f.kind is FUSE_NONE)
+void launch_vmult_fused(const CellView& c, int dtype, int nv, void* dst_acc, const void* src, const FusedStep& f,
+                        hipStream_t s);
 // diag (FP64) = diagonal of A
 void launch_diagonal(const CellView& c, double* diag, hipStream_t s);
 // b (FP64) += load vector; kind 0 const, 1 gaussians (params on device, n_terms per vector)

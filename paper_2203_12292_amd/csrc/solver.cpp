@@ -341,24 +341,60 @@ void level_smooth(Context& ctx, int l, int nv, void* x, const void* b, bool x_is
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
+  // each operator application on one vector carries the Chebyshev update of
+  // its output (exclusive DoFs in the batch kernel, shared DoFs in the
+  // reduction); several interleaved vectors, which the operator handles one
+  // after the other, are updated by the contiguous vector kernel instead
+  if (nv > 1) {
+    if (x_is_zero) {
+      launch_cheb_step(dt, L.n_dofs, nv, true, 0.0, 1.0 / theta, nullptr, b, dinv, L.d.ptr, x, s);
+    } else {
+      launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
+      launch_cheb_step(dt, L.n_dofs, nv, false, 0.0, 1.0 / theta, L.t.ptr, b, dinv, L.d.ptr, x, s);
+    }
+    for (int it = 1; it < ctx.cheb_degree; ++it) {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
+      launch_cheb_step(dt, L.n_dofs, nv, false, rho_new * rho, 2.0 * rho_new / delta, L.t.ptr, b, dinv, L.d.ptr, x,
+                       s);
+      rho = rho_new;
+    }
+    return;
+  }
+  FusedStep f;
+  f.kind = FUSE_CHEB;
+  f.b = b;
+  f.dinv = dinv;
+  f.d = L.d.ptr;
+  f.x = x;
   if (x_is_zero) {
     launch_cheb_step(dt, L.n_dofs, nv, true, 0.0, 1.0 / theta, nullptr, b, dinv, L.d.ptr, x, s);
   } else {
-    launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
-    launch_cheb_step(dt, L.n_dofs, nv, false, 0.0, 1.0 / theta, L.t.ptr, b, dinv, L.d.ptr, x, s);
+    f.c_dd = 0.0;
+    f.c_r = 1.0 / theta;
+    launch_vmult_fused(L.view, dt, nv, nullptr, x, f, s);
   }
   for (int it = 1; it < ctx.cheb_degree; ++it) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    launch_vmult(L.view, dt, nv, L.t.ptr, x, s);
-    launch_cheb_step(dt, L.n_dofs, nv, false, rho_new * rho, 2.0 * rho_new / delta, L.t.ptr, b, dinv, L.d.ptr, x, s);
+    f.c_dd = rho_new * rho;
+    f.c_r = 2.0 * rho_new / delta;
+    launch_vmult_fused(L.view, dt, nv, nullptr, x, f, s);
     rho = rho_new;
   }
 }
 
 void level_residual(Context& ctx, int l, int nv, void* r, const void* b, const void* x, hipStream_t s) {
   Level& L = ctx.level(l);
-  launch_vmult(L.view, L.dtype, nv, L.t.ptr, x, s);
-  launch_residual_update(L.dtype, L.n_dofs * nv, b, L.t.ptr, r, s);
+  if (nv > 1) {  // (see level_smooth)
+    launch_vmult(L.view, L.dtype, nv, L.t.ptr, x, s);
+    launch_residual_update(L.dtype, L.n_dofs * nv, b, L.t.ptr, r, s);
+    return;
+  }
+  FusedStep f;  // r = b - A x on the operator's output
+  f.kind = FUSE_RESIDUAL;
+  f.b = b;
+  f.r = r;
+  launch_vmult_fused(L.view, L.dtype, nv, nullptr, x, f, s);
 }
 
 void level_prolongate_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s) {
