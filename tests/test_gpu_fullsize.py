@@ -155,3 +155,33 @@ def test_neumann_constants_full_size_q4():
     print(f"[neumann] {one.numel()} DoFs: max |A 1| / max diag = {ratio:.2e}", flush=True)
     assert ratio <= 1e-12 and float(d.min()) > 0.0
     S.close()
+
+
+@pytest.mark.parametrize("name", ["cube16_ball4_q4", "cube12_spheres_q6"])
+def test_transfers_full_size_galerkin_and_duality(name):
+    """Every level pair of the full-size hierarchies (global coarsening, and
+    Q6 -> Q3 -> Q1): the spaces are nested and the quadrature is exact, so
+    (P x)^T A_f (P x) = x^T A_c x for any coarse x (P^T A_f P = A_c), and
+    restriction is the transpose, z . (P x) = (R z) . x.  FP64 kernels on
+    all levels, seeded vectors, relative tolerance 1e-11."""
+    S = workload(name)[0]
+    g = torch.Generator(device=DEV).manual_seed(12292)
+    for l in range(1, S.n_levels):
+        nf, nc = S.n_dofs(l), S.n_dofs(l - 1)
+        xc = torch.rand(nc, dtype=torch.float64, device=DEV, generator=g) * 2 - 1
+        zf = torch.rand(nf, dtype=torch.float64, device=DEV, generator=g) * 2 - 1
+        yf = torch.zeros(nf, dtype=torch.float64, device=DEV)
+        S.prolongate_add(l, yf, xc)
+        rc = torch.zeros(nc, dtype=torch.float64, device=DEV)
+        S.restrict_add(l, rc, zf)
+        af, ac = torch.empty_like(yf), torch.empty_like(xc)
+        S.vmult(l, af, yf)
+        S.vmult(l - 1, ac, xc)
+        torch.cuda.synchronize()
+        e_f, e_c = float(torch.dot(yf, af)), float(torch.dot(xc, ac))
+        d_f, d_c = float(torch.dot(zf, yf)), float(torch.dot(rc, xc))
+        scale = float((zf.abs() * yf.abs()).sum())
+        print(f"[galerkin] {name} level {l}: {nf}/{nc} DoFs, energy {e_f:.12e} vs {e_c:.12e}, "
+              f"duality {abs(d_f - d_c) / scale:.1e}", flush=True)
+        assert abs(e_f - e_c) <= 1e-11 * abs(e_c), l
+        assert abs(d_f - d_c) <= 1e-12 * scale, l
