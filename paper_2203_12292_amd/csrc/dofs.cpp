@@ -202,7 +202,7 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
     };
     for (int64_t c = 0; c < nc; ++c) {
       int64_t add = added(c);
-      if (in_batch > 0 && (local + add > mcap || in_batch >= BATCH_MAX_CELLS)) {
+      if (in_batch > 0 && (local + add > mcap || in_batch >= batch_max_cells(k))) {
         const int64_t keep = in_batch > quantum ? in_batch / quantum * quantum : in_batch;
         c = start + keep;
         L.batch_cell_off.push_back(static_cast<int32_t>(c));

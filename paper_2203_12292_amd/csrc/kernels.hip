@@ -580,6 +580,8 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
   __shared__ T in_[MCAP + NZ];
   __shared__ double out_[MCAP + NZ];  // contributions accumulate in FP64 (also for FP32 arithmetic)
   __shared__ T Hg[2 * N2];
+  constexpr bool META_LDS = batch_meta_in_lds(K);
+  __shared__ CellMeta metaL[META_LDS ? batch_max_cells(K) : 1];
   __shared__ T buf0[(BATCH_WAVES * CPW + 1) * N3];
   __shared__ T buf1[(BATCH_WAVES * CPW + 1) * N3];
   for (int i = threadIdx.x; i < NZ; i += BT) in_[ZB + i] = T(0);
@@ -645,9 +647,14 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
     // unconditional, from the batch's first cell for lanes without a cell, so
     // that the wait for them can be counted exactly; such lanes then point at
     // the zero block)
+    if constexpr (META_LDS) {  // the batch's cell records, 16 bytes per thread
+      const uint4* gsrc = reinterpret_cast<const uint4*>(meta + c0);
+      uint4* ldst = reinterpret_cast<uint4*>(metaL);
+      for (int i = threadIdx.x; i < (c1 - c0) * 4; i += BT) ldst[i] = gsrc[i];
+    }
     auto fetch = [&](int64_t cell) {
       const bool ok = lane_used && cell < c1;
-      const CellMeta* M = meta + (ok ? cell : c0);
+      const CellMeta* M = META_LDS ? metaL + (ok ? cell - c0 : 0) : meta + (ok ? cell : c0);
       const uint16_t* L = M->loc;
       Pre p{L[gs0], L[gs1], L[gsm], L[ss0], L[ss1], L[ssm], M->mask};
       p.g0 = ok ? p.g0 : ZB;
@@ -660,8 +667,9 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
       return p;
     };
     int cw = c0 + wave * CPW;
+    if constexpr (META_LDS) __syncthreads();
     Pre nx = fetch(cw + lc);
-    __syncthreads();
+    if constexpr (!META_LDS) __syncthreads();
     for (; cw < c1; cw += BATCH_WAVES * CPW) {
       const Pre cur = nx;
       nx = fetch(cw + BATCH_WAVES * CPW + lc);

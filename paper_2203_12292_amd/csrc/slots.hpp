@@ -77,6 +77,12 @@ __host__ __device__ constexpr int cells_per_wave(int n) { return 64 / (n * n); }
 #endif
 constexpr int BATCH_LDS_BYTES = MFMG_BATCH_LDS_BYTES;
 constexpr int BATCH_MAX_CELLS = 1024;
+// From degree 5 on, the batch's cell metadata (64 B per cell) is staged in
+// LDS too, for at most two cell groups of the block per batch.
+__host__ __device__ constexpr bool batch_meta_in_lds(int k) { return k >= 5; }
+__host__ __device__ constexpr int batch_max_cells(int k) {
+  return batch_meta_in_lds(k) ? 2 * BATCH_WAVES * cells_per_wave(k + 1) : BATCH_MAX_CELLS;
+}
 #ifndef MFMG_BATCH_QUANTIZE
 #define MFMG_BATCH_QUANTIZE 1
 #endif
@@ -89,8 +95,10 @@ constexpr int BATCH_GRID_FACTOR = MFMG_BATCH_GRID_FACTOR;
 __host__ __device__ constexpr int batch_zero_entries(int k) { return k > 1 ? (k - 1) * (k - 1) * (k - 1) : 1; }
 __host__ __device__ constexpr int batch_work_bytes(int k) {
   // two n^3 buffers per cell of every wavefront plus one spare pair for lanes
-  // without a cell, and the hanging-interpolation matrices of both halves
-  return (BATCH_WAVES * cells_per_wave(k + 1) + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8 + 2 * (k + 1) * (k + 1) * 8;
+  // without a cell, the hanging-interpolation matrices of both halves and the
+  // staged cell metadata
+  return (BATCH_WAVES * cells_per_wave(k + 1) + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8 + 2 * (k + 1) * (k + 1) * 8 +
+         (batch_meta_in_lds(k) ? batch_max_cells(k) * 64 : 0);
 }
 __host__ __device__ constexpr int batch_mcap(int k) {
   return ((BATCH_LDS_BYTES - batch_work_bytes(k)) / 16 - batch_zero_entries(k)) / 64 * 64;
