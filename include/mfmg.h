@@ -243,7 +243,7 @@ int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk);
  * the coarse right-hand side at the cell's (k+1)^3 nodes divided by
  * s = ||b0||_2 and the cell centre; two hidden layers of width 64 (GELU);
  * output the cell's nodal correction divided by s; nodes of several cells
- * average their cells' outputs.  The exact coarse solve judges every
+ * average their cells' outputs.  The exact coarse operator checks every
  * prediction: if ||b0 - A0 y||_2 > tau ||b0||_2 the exact solution is used.
  * Flat FP32 parameters: W1 ((nq+3) x 64, row-major), b1, W2 (64x64), b2,
  * W3 (64 x nq), b3, nq = (k+1)^3 of level 0.  Requires a coarse level
@@ -273,7 +273,7 @@ int mfmg_net_loss_grad(mfmg_ctx ctx, int n_rows, const float* X, const float* T,
  * history (host, `epochs` floats, may be NULL) gets the data-set loss after
  * each epoch.  Synchronous. */
 int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history);
-/* Coarse solver of the V-cycle: MFMG_COARSE_EXACT, _LEARNED (with judge and
+/* Coarse solver of the V-cycle: MFMG_COARSE_EXACT, _LEARNED (with residual check and
  * fallback, threshold tau) or _ZERO (no coarse correction; for comparison). */
 int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau);
 /* Number of learned predictions accepted / rejected since the last call and

@@ -254,12 +254,12 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// Step 2 (one block): the exact coarse operator judges the prediction y; if
+// Step 2 (one block): the exact coarse operator checks the prediction y; if
 // ||b0 - A0 y|| > tau ||b0|| the exact solution A0^{-1} b0 is used instead.
 // mode 2: no coarse correction (x = 0).
 template <typename S>
 __global__ void __launch_bounds__(256)
-    net_judge(int n0, const double* __restrict__ A, const double* __restrict__ Ainv, double tau, int mode,
+    net_check(int n0, const double* __restrict__ A, const double* __restrict__ Ainv, double tau, int mode,
               const S* __restrict__ b, S* __restrict__ x, const double* __restrict__ work,
               int* __restrict__ counters, double* __restrict__ relsum) {
   __shared__ double red[256];
@@ -485,7 +485,7 @@ static void net_coarse_solve_t(Context& ctx, S* x, const S* b, hipStream_t s) {
     net_infer_cells<S><<<N.n_cells, 64, 0, s>>>(N.n0, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
                                                  N.centre.ptr, b, N.work.ptr);
   }
-  net_judge<S><<<1, 256, 0, s>>>(N.n0, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode, b, x, N.work.ptr,
+  net_check<S><<<1, 256, 0, s>>>(N.n0, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode, b, x, N.work.ptr,
                                  N.counters.ptr, N.relsum.ptr);
   check_launch();
 }

@@ -3,7 +3,7 @@
 * Gradients of the HIP forward/backward kernels (FP32) against the FP64
   oracle backward (itself checked by finite differences in
   test_oracle_mlp.py): relative error <= 1e-4.
-* The exact coarse solve judges every prediction: a network that predicts 0
+* The exact coarse operator checks every prediction: a network that predicts 0
   is always rejected and the solve is then identical to the exact one.
 * Gain: after training on coarse right-hand sides recorded from the solver,
   the learned correction is compared with the exact coarse solve and with no

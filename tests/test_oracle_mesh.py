@@ -74,7 +74,8 @@ def test_closure_is_idempotent_and_balanced():
 
 
 def test_workload_meshes_sizes():
-    # the benchmark meshes under the readings stated in the design doc
+    # the benchmark meshes: ball steps towards the origin corner of [0,1]^3 (cell
+    # centres within the radius), sphere-cut steps on [-1,1]^3
     seq = [m.n_leaves() for m in octree.gc_sequence(octree.build_mesh(synth.CFG1))]
     assert seq == [2808, 428, 113, 64]
     seq = [m.n_leaves() for m in octree.gc_sequence(octree.build_mesh(synth.CFG1_TINY))]
