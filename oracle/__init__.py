@@ -20,6 +20,9 @@ for FEM computations", arXiv 2203.12292):
 * ``solvers`` — Chebyshev-Jacobi smoothing (Section 3.3), the V-cycle of
   Algorithms 1-2 (global-coarsening branch), CG preconditioned by one V-cycle
   (Section 2), direct solves.
+* ``local_smoothing`` — the local-smoothing levels (all cells of one
+  refinement level), their refinement-edge split, the copy to and from the
+  levels, and the local-smoothing branch of Algorithms 1-2 (Section 2.1).
 * ``mlp``     — the per-coarse-cell network of the learned coarse correction
   (forward, backward, Adam) in FP64.
 
