@@ -82,7 +82,20 @@ typedef struct {
  *           (Section 2.3), then geometric global coarsening at degree 1;
  *  H_THEN_P geometric global coarsening at the fine degree, then polynomial
  *           coarsening on the coarse grid (keeps the coarse problem small). */
-enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2 };
+/*  LS       geometric local smoothing (Section 2.1): level l holds every
+ *           cell of refinement level l, refined or not (no hanging nodes);
+ *           DoFs where such a level ends inside the domain form the
+ *           refinement edge.  The V-cycle follows the local-smoothing branch
+ *           of Algorithm 2 and the copy to and from the levels of
+ *           Algorithm 1; the outer solver works on the leaves (the active
+ *           mesh, level index MFMG_LEVEL_ACTIVE).  Needs dirichlet = 1 and
+ *           one storage type for all levels. */
+enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2, MFMG_SCHEME_LS = 3 };
+
+/* Level index of the active mesh (the leaves) in every call that takes a
+ * level: the finest level under global coarsening, the operator of the leaves
+ * with its hanging-node constraints under local smoothing. */
+#define MFMG_LEVEL_ACTIVE (-1)
 
 typedef struct {
   int degree;            /* finest degree k, 1 <= k <= 6 */
@@ -137,7 +150,8 @@ int mfmg_setup_levels(mfmg_mesh mesh, const mfmg_level_desc* desc, void* stream,
 
 int mfmg_n_levels(mfmg_ctx ctx, int* n_levels);
 
-/* level: 0 = coarsest.  Any output pointer may be NULL. */
+/* level: 0 = coarsest, MFMG_LEVEL_ACTIVE = the active mesh.  Any output
+ * pointer may be NULL. */
 int mfmg_level_info(mfmg_ctx ctx, int level, int64_t* n_dofs, int64_t* n_cells, int* degree,
                     int* dtype, int64_t* n_hanging_cells);
 
@@ -159,6 +173,17 @@ int mfmg_smoother_range(mfmg_ctx ctx, int level, double* lambda_min, double* lam
  * ([n_dofs][n_dofs] row-major, only for n_dofs <= 20000) are filled. */
 int mfmg_host_level_matrix(mfmg_mesh mesh, int mesh_index, int degree, int dirichlet, int64_t* n_dofs,
                            int64_t* codes, double* dense);
+
+/* Host-only inspection of a local-smoothing level (Section 2.1): all cells of
+ * refinement level `level` of the finest mesh at degree k, Dirichlet
+ * boundary.  Call with every array NULL to get *n_dofs and *n_copy; then
+ * codes ([n_dofs][3]), edge (one byte per DoF, 1 = refinement edge), dense
+ * (the assembled level matrix incl. edge rows, n_dofs <= 20000) and the copy
+ * map of Algorithm 1 (copy_level[q] <-> copy_active[q], active DoFs numbered
+ * as by mfmg_host_level_matrix on the finest mesh) may be filled. */
+int mfmg_host_ls_level(mfmg_mesh mesh, int level, int degree, int64_t* n_dofs, int64_t* n_copy,
+                       int64_t* codes, uint8_t* edge, double* dense, int32_t* copy_level,
+                       int32_t* copy_active);
 
 /* ---- hot path (device; [async] on `stream`) ----------------------------- */
 
@@ -202,10 +227,35 @@ int mfmg_restrict_add(mfmg_ctx ctx, int fine_level, int dtype, int n_vec, void* 
  * does nothing. */
 int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b, void* stream);
 
-/* [async] Algorithm 1: copy b (FP64) to the finest level in that level's
- * storage type, one V-cycle (Algorithm 2, global-coarsening branch), copy x
- * back to FP64.  n_vec <= max_rhs. */
+/* [async] Algorithm 1: copy b (FP64, active mesh) to the levels in their
+ * storage type, one V-cycle (Algorithm 2: global-coarsening branch, or the
+ * local-smoothing branch under MFMG_SCHEME_LS), copy x back to FP64.
+ * n_vec <= max_rhs. */
 int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* stream);
+
+/* [async] Algorithm 1, copy to the levels, for level l: dst (level storage
+ * type, [n_dofs(l)][n_vec]) is zeroed, then receives the values of the
+ * active-mesh vector src (FP64) at the active DoFs that belong to level l.
+ * Under global coarsening l must be the finest level and dst = src (cast).
+ * Under local smoothing an active DoF belongs to the coarsest level among
+ * the leaves that have it as a node, where it is an interior (non-edge) DoF;
+ * every active DoF belongs to exactly one level. */
+int mfmg_copy_to_mg(mfmg_ctx ctx, int level, int n_vec, void* dst, const void* src_f64, void* stream);
+
+/* [async] Algorithm 1, copy from the levels: the active DoFs that belong to
+ * level l (as in mfmg_copy_to_mg) receive their values from src (level
+ * storage type); the other entries of dst (FP64) are left unchanged. */
+int mfmg_copy_from_mg(mfmg_ctx ctx, int level, int n_vec, void* dst_f64, const void* src, void* stream);
+
+/* Refinement-edge DoFs of level l (Section 2.1, local smoothing): their
+ * number in *n_edge and, if flags is not NULL, one byte per DoF (host array
+ * [n_dofs(l)], 1 = edge).  Smoothing treats them as Dirichlet values (their
+ * inverse diagonal is 0, so A_SS acts on the interior DoFs and the smoother
+ * keeps x_E); the residual step gives -A_ES x_S on them, and after the
+ * prolongation the smoother's operator applies A_SE x_E, i.e. the modified
+ * right-hand side b_S - A_SE x_E of the edge step.  0 under global
+ * coarsening. */
+int mfmg_level_edge(mfmg_ctx ctx, int level, int64_t* n_edge, uint8_t* flags);
 
 /* FP64 conjugate gradients preconditioned by one V-cycle per iteration
  * (Section 2), x0 = 0, stopped when ||b - A x||_2 <= rtol ||b||_2 for every

@@ -117,6 +117,34 @@ int mfmg_host_level_matrix(mfmg_mesh mesh, int mesh_index, int degree, int diric
   });
 }
 
+int mfmg_host_ls_level(mfmg_mesh mesh, int level, int degree, int64_t* n_dofs, int64_t* n_copy, int64_t* codes,
+                       uint8_t* edge, double* dense, int32_t* copy_level, int32_t* copy_active) {
+  return guarded([&] {
+    check_ptr(mesh, "mesh");
+    check_ptr(n_dofs, "n_dofs");
+    check_ptr(n_copy, "n_copy");
+    const mfmg::Octree& tree = mesh->gc.back();
+    MFMG_REQUIRE(level >= 0 && level <= tree.n_levels() && (level == 0 || !tree.refined[level - 1].empty()),
+                 MFMG_ERR_INVALID_ARG, "refinement level without cells");
+    mfmg::LevelDofs H = mfmg::build_level_dofs(tree, degree, true, codes != nullptr, level);
+    mfmg::LevelDofs A = mfmg::build_level_dofs(tree, degree, true, false);
+    std::vector<int32_t> cl, ca;
+    mfmg::ls_copy_pairs(H, A, mfmg::EntityIndex(A), cl, ca);
+    *n_dofs = H.n_dofs;
+    *n_copy = static_cast<int64_t>(cl.size());
+    if (codes) std::memcpy(codes, H.codes.data(), H.codes.size() * sizeof(int64_t));
+    if (edge) std::memcpy(edge, H.dof_edge.data(), H.dof_edge.size());
+    if (copy_level) std::memcpy(copy_level, cl.data(), cl.size() * sizeof(int32_t));
+    if (copy_active) std::memcpy(copy_active, ca.data(), ca.size() * sizeof(int32_t));
+    if (dense) {
+      MFMG_REQUIRE(H.n_dofs <= 20000, MFMG_ERR_UNSUPPORTED, "dense matrix too large");
+      std::vector<double> M = mfmg::assemble_dense(H, mfmg::Tables1D(degree));
+      std::memcpy(dense, M.data(), M.size() * sizeof(double));
+    }
+    return MFMG_OK;
+  });
+}
+
 int mfmg_setup_levels(mfmg_mesh mesh, const mfmg_level_desc* desc, void* stream, mfmg_ctx* out) {
   return guarded([&] {
     check_ptr(mesh, "mesh");
@@ -170,7 +198,8 @@ int mfmg_level_dof_codes(mfmg_ctx ctx, int level, int64_t* codes) {
     check_ptr(ctx, "ctx");
     check_ptr(codes, "codes");
     mfmg::Level& L = ctx->ctx.level(level);
-    mfmg::LevelDofs H = mfmg::build_level_dofs(ctx->ctx.meshes[L.mesh], L.k, ctx->ctx.desc.dirichlet != 0);
+    mfmg::LevelDofs H =
+        mfmg::build_level_dofs(ctx->ctx.meshes[L.mesh], L.k, ctx->ctx.desc.dirichlet != 0, true, L.only_level);
     MFMG_REQUIRE(H.n_dofs == L.n_dofs, MFMG_ERR_INVALID_ARG, "inconsistent level");
     std::memcpy(codes, H.codes.data(), H.codes.size() * sizeof(int64_t));
     return MFMG_OK;
@@ -233,6 +262,7 @@ int mfmg_smooth(mfmg_ctx ctx, int level, int dtype, int n_vec, void* x, const vo
     mfmg::Level& L = ctx->ctx.level(level);
     MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
     MFMG_REQUIRE(dtype == L.dtype, MFMG_ERR_INVALID_ARG, "dtype must equal the level's storage type");
+    MFMG_REQUIRE(L.d.ptr != nullptr || L.n_dofs == 0, MFMG_ERR_UNSUPPORTED, "no smoother on the active mesh");
     check_vec(x, L.n_dofs, "x");
     check_vec(b, L.n_dofs, "b");
     double lmin = L.lmin, lmax = L.lmax;
@@ -319,6 +349,45 @@ int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* s
     if (ctx->ctx.fine().n_dofs == 0) return MFMG_OK;
     mfmg::vcycle(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64),
                  as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_copy_to_mg(mfmg_ctx ctx, int level, int n_vec, void* dst, const void* src_f64, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+    mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(dst, L.n_dofs, "dst");
+    check_vec(src_f64, ctx->ctx.fine().n_dofs, "src");
+    if (L.n_dofs == 0) return MFMG_OK;
+    mfmg::copy_to_mg(ctx->ctx, level, n_vec, dst, static_cast<const double*>(src_f64), as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_copy_from_mg(mfmg_ctx ctx, int level, int n_vec, void* dst_f64, const void* src, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    MFMG_REQUIRE(n_vec >= 1 && n_vec <= ctx->ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+    mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(src, L.n_dofs, "src");
+    check_vec(dst_f64, ctx->ctx.fine().n_dofs, "dst");
+    if (L.n_dofs == 0) return MFMG_OK;
+    mfmg::copy_from_mg(ctx->ctx, level, n_vec, static_cast<double*>(dst_f64), src, as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_level_edge(mfmg_ctx ctx, int level, int64_t* n_edge, uint8_t* flags) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    mfmg::Level& L = ctx->ctx.level(level);
+    if (n_edge) *n_edge = L.n_edge;
+    if (flags) {
+      if (L.host_edge.empty()) std::memset(flags, 0, static_cast<size_t>(L.n_dofs));
+      else std::memcpy(flags, L.host_edge.data(), L.host_edge.size());
+    }
     return MFMG_OK;
   });
 }

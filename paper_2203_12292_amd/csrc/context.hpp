@@ -18,6 +18,7 @@ namespace mfmg {
 
 struct Level {
   int mesh = 0;     // index into the global-coarsening sequence
+  int only_level = -1;  // local smoothing: the refinement level whose cells form this level
   int k = 1;
   int dtype = MFMG_F64;
   int64_t n_dofs = 0, n_cells = 0, n_hanging = 0;
@@ -38,6 +39,11 @@ struct Level {
   DeviceArray<int32_t> tr_ident_c, tr_ident_f, tr_ref_c, tr_ref_f;
   DeviceArray<uint8_t> tr_valence;
   TransferView tview;
+  // local smoothing: refinement-edge DoFs, and the copy to / from the active
+  // mesh (level DoF cp_level[q] <-> active DoF cp_active[q])
+  int64_t n_edge = 0, n_copy = 0;
+  std::vector<uint8_t> host_edge;
+  DeviceArray<int32_t> edge_idx, cp_level, cp_active;
 };
 
 struct NetState {
@@ -62,6 +68,10 @@ struct Context {
   mfmg_level_desc desc{};
   std::vector<Octree> meshes;
   std::vector<Level> levels;  // 0 = coarsest
+  // local smoothing: `levels` are the refinement levels and `active` is the
+  // operator of the leaves (the mesh the outer solver works on)
+  bool ls = false;
+  Level active;
   int max_rhs = 1;
   int cheb_degree = 3;
   // exact coarse solver: dense inverse of A^(0)
@@ -75,8 +85,10 @@ struct Context {
   std::vector<double> host_scalar;
   hipStream_t stream = nullptr;
 
-  Level& fine() { return levels.back(); }
+  Level& fine() { return ls ? active : levels.back(); }
+  // level -1 addresses the active mesh
   Level& level(int l) {
+    if (l == MFMG_LEVEL_ACTIVE) return fine();
     MFMG_REQUIRE(l >= 0 && l < static_cast<int>(levels.size()), MFMG_ERR_INVALID_ARG, "level out of range");
     return levels[l];
   }
@@ -93,6 +105,8 @@ void level_prolongate_add(Context& ctx, int fine, int dtype, int nv, void* dst, 
 void level_restrict_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s);
 void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipStream_t s);
 void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s);
+void copy_to_mg(Context& ctx, int l, int nv, void* dst, const double* src, hipStream_t s);
+void copy_from_mg(Context& ctx, int l, int nv, double* dst, const void* src, hipStream_t s);
 int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,
         mfmg_solve_stats* stats, hipStream_t s);
 

@@ -68,13 +68,15 @@ struct EntityRec {
   int64_t i, j, k;
   int slot;
   int32_t first_dof;
+  uint64_t key;
+  uint8_t around;  // cells of the mesh's level inside the domain that contain the entity
 };
 
 }  // namespace
 
 bool LevelDofs::slot_hanging(int64_t c, int s) const { return mfmg::slot_hanging(mask[c], s); }
 
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes) {
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes, int only_level) {
   MFMG_REQUIRE(k >= 1 && k <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   LevelDofs L;
   L.k = k;
@@ -84,7 +86,8 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
                "mesh too fine for 21-bit entity coordinates");
 
   // cells along the Morton curve of their lower corner on the finest lattice
-  std::vector<Cell> cells = tree.leaves();
+  const bool ls_level = only_level >= 0;
+  std::vector<Cell> cells = ls_level ? tree.cells_of_level(only_level) : tree.leaves();
   {
     std::vector<std::pair<uint64_t, int64_t>> order(cells.size());
     for (size_t c = 0; c < cells.size(); ++c) {
@@ -108,7 +111,9 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   for (int64_t c = 0; c < nc; ++c) {
     const Cell& x = cells[c];
     uint32_t m = static_cast<uint32_t>(x.level) << MASK_LEVEL_SHIFT;
-    if (x.level > 0) {
+    if (ls_level) {
+      m |= static_cast<uint32_t>((x.i & 1) | (x.j & 1) << 1 | (x.k & 1) << 2);
+    } else if (x.level > 0) {
       const int64_t p[3] = {x.i, x.j, x.k};
       int s[3], o[3];
       for (int d = 0; d < 3; ++d) {
@@ -158,24 +163,31 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
       int64_t D[3];
       const int64_t q[3] = {owner.i, owner.j, owner.k};
       bool boundary = false;
+      int around = 1;
       for (int d = 0; d < 3; ++d) {
         const int sd = slot_side(s, d);
         D[d] = sd < 0 ? (2 * q[d] + 1) << sh : (2 * (q[d] + sd)) << sh;
         if (sd >= 0 && (D[d] == 0 || D[d] == dmax)) boundary = true;
+        if (sd >= 0 && D[d] != 0 && D[d] != dmax) around *= 2;
       }
       if (dirichlet && boundary) continue;
       const uint64_t key = (static_cast<uint64_t>(D[0]) << 42) | (static_cast<uint64_t>(D[1]) << 21) |
                            static_cast<uint64_t>(D[2]);
       bool inserted;
       int32_t id = map.find_or_insert(key, static_cast<int32_t>(ents.size()), inserted);
-      if (inserted) ents.push_back({owner.level, owner.i, owner.j, owner.k, s, -1});
+      if (inserted)
+        ents.push_back({owner.level, owner.i, owner.j, owner.k, s, -1, key, static_cast<uint8_t>(around)});
       L.ent_id[s * nc + c] = id;
     }
   }
   const int64_t n_bent = static_cast<int64_t>(ents.size());  // boundary-of-cell entities
   for (int64_t c = 0; c < nc; ++c) {
     L.ent_id[26 * nc + c] = static_cast<int32_t>(n_bent + c);
-    ents.push_back({cells[c].level, cells[c].i, cells[c].j, cells[c].k, 26, -1});
+    const int sh = top - cells[c].level;
+    const uint64_t key = (static_cast<uint64_t>((2 * cells[c].i + 1) << sh) << 42) |
+                         (static_cast<uint64_t>((2 * cells[c].j + 1) << sh) << 21) |
+                         static_cast<uint64_t>((2 * cells[c].k + 1) << sh);
+    ents.push_back({cells[c].level, cells[c].i, cells[c].j, cells[c].k, 26, -1, key, 1});
   }
   const int64_t ne = static_cast<int64_t>(ents.size());
   L.n_entities = ne;
@@ -339,6 +351,39 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
     for (size_t p = 0; p < L.sh_idx.size(); ++p) L.red_idx[fill[L.sh_idx[p]]++] = static_cast<int32_t>(p);
   }
   for (size_t e = 0; e < ents.size(); ++e) ents[e].first_dof = static_cast<int32_t>(start[e]);
+  L.ent_key.resize(ne);
+  L.ent_first.resize(ne);
+  L.ent_size.resize(ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    L.ent_key[e] = ents[e].key;
+    L.ent_first[e] = ents[e].first_dof;
+    L.ent_size[e] = static_cast<int32_t>(esize(e));
+  }
+  if (ls_level) {
+    // refinement edge: fewer cells of this level contain the entity than lie
+    // around it inside the domain (the rest of its surroundings is covered by
+    // coarser leaves)
+    std::vector<uint8_t> count(ne, 0);
+    L.ent_on_leaf.assign(ne, 0);
+    for (int64_t c = 0; c < nc; ++c) {
+      const Cell& x = L.cells[c];
+      const bool leaf = !tree.is_refined(x.level, x.i, x.j, x.k);
+      for (int s = 0; s < N_SLOTS; ++s) {
+        const int32_t id = L.ent_id[s * nc + c];
+        if (id < 0) continue;
+        if (s < 26) ++count[id];
+        if (leaf) L.ent_on_leaf[id] = 1;
+      }
+    }
+    L.ent_edge.assign(ne, 0);
+    L.dof_edge.assign(L.n_dofs, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+      if (ents[e].slot == 26 || count[e] >= ents[e].around) continue;
+      L.ent_edge[e] = 1;
+      for (int t = 0; t < L.ent_size[e]; ++t) L.dof_edge[L.ent_first[e] + t] = 1;
+      L.n_edge_dofs += L.ent_size[e];
+    }
+  }
 
   if (!want_codes) return L;
   // exact node codes of every DoF
@@ -360,7 +405,7 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   return L;
 }
 
-TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial) {
+TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial, bool skip_unrefined) {
   TransferDofs T;
   T.polynomial = polynomial;
   const int64_t nf = fine.n_cells, ncc = coarse.n_cells;
@@ -401,6 +446,8 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
         T.ident_coarse.push_back(static_cast<int32_t>(c));
         T.ident_fine.push_back(f);
         group_cells.push_back(f);
+      } else if (skip_unrefined && find(x.level + 1, 2 * x.i, 2 * x.j, 2 * x.k) < 0) {
+        // an active coarse cell of a local-smoothing level: no transfer group
       } else {
         T.refined_coarse.push_back(static_cast<int32_t>(c));
         for (int ch = 0; ch < 8; ++ch) {
@@ -452,6 +499,28 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
       T.valence[s * nf + c] = count[id];
     }
   return T;
+}
+
+EntityIndex::EntityIndex(const LevelDofs& active) {
+  by_key.reserve(active.ent_key.size() * 2);
+  for (size_t e = 0; e < active.ent_key.size(); ++e)
+    if (active.ent_first[e] >= 0) by_key.emplace(active.ent_key[e], static_cast<int32_t>(e));
+}
+
+void ls_copy_pairs(const LevelDofs& H, const LevelDofs& A, const EntityIndex& index, std::vector<int32_t>& cl,
+                   std::vector<int32_t>& ca) {
+  cl.clear();
+  ca.clear();
+  for (size_t e = 0; e < H.ent_key.size(); ++e) {
+    if (H.ent_first[e] < 0 || !H.ent_on_leaf[e] || H.ent_edge[e]) continue;
+    auto it = index.by_key.find(H.ent_key[e]);
+    MFMG_REQUIRE(it != index.by_key.end() && A.ent_size[it->second] == H.ent_size[e], MFMG_ERR_INVALID_ARG,
+                 "copy map: level entity without an active counterpart");
+    for (int t = 0; t < H.ent_size[e]; ++t) {
+      cl.push_back(H.ent_first[e] + t);
+      ca.push_back(A.ent_first[it->second] + t);
+    }
+  }
 }
 
 namespace {

@@ -39,6 +39,7 @@
 #pragma once
 
 #include <cstdint>
+#include <unordered_map>
 #include <vector>
 
 #include "octree.hpp"
@@ -75,12 +76,24 @@ struct LevelDofs {
   std::vector<uint16_t> loc;            // [N_SLOTS][n_cells] local entity start, 0xffff Dirichlet
   std::vector<int32_t> red_off;         // [n_shared+1] CSR over the shared DoFs
   std::vector<int32_t> red_idx;         // partial-buffer positions (batch order) of each shared DoF
+  // entities: key (doubled centre coordinates on the finest lattice of the
+  // tree), first DoF and DoF count
+  std::vector<uint64_t> ent_key;
+  std::vector<int32_t> ent_first, ent_size;
+  // local-smoothing levels only: per entity, lies on the refinement edge /
+  // belongs to a cell that is a leaf of the tree; per DoF, the edge flag
+  std::vector<uint8_t> ent_edge, ent_on_leaf, dof_edge;
+  int64_t n_edge_dofs = 0;
   bool slot_hanging(int64_t c, int s) const;
 };
 
 // Builds the DoF numbering and gather maps of `tree` at degree k; `codes`
-// also computes the position codes of all DoFs.
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true);
+// also computes the position codes of all DoFs.  With only_level >= 0 the
+// cells are all cells of that refinement level, refined or not (a
+// local-smoothing level, Section 2.1: a conforming mesh of the region they
+// cover, without hanging nodes); DoFs on the boundary of that region inside
+// the domain are flagged as refinement-edge DoFs.
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true, int only_level = -1);
 
 // Transfer data between a fine level and the next coarser one (Section 3.5).
 // Geometric: every coarse cell is a fine cell (identity category) or the
@@ -96,7 +109,22 @@ struct TransferDofs {
   std::vector<uint8_t> valence;                    // [N_SLOTS][n_fine_cells]
 };
 
-TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial);
+// With skip_unrefined, coarse cells that are neither fine cells nor parents of
+// fine cells are left out (local-smoothing levels: the active coarse cells
+// take no part in the transfer).
+TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial,
+                            bool skip_unrefined = false);
+
+// Copy between the active mesh and a local-smoothing level (Algorithm 1):
+// the interior (non-edge) entities of the level's leaves are entities of the
+// active mesh with the same key and DoF layout; their DoFs are paired as
+// (level DoF, active DoF).
+struct EntityIndex {
+  std::unordered_map<uint64_t, int32_t> by_key;
+  explicit EntityIndex(const LevelDofs& active);
+};
+void ls_copy_pairs(const LevelDofs& level, const LevelDofs& active, const EntityIndex& index,
+                   std::vector<int32_t>& level_dofs, std::vector<int32_t>& active_dofs);
 
 // Dense assembled matrix of a (small) level: sum_e C_e^T A_e C_e.
 std::vector<double> assemble_dense(const LevelDofs& L, const struct Tables1D& t);

@@ -1179,6 +1179,29 @@ __global__ void cast_kernel(int64_t n, const A* __restrict__ src, B* __restrict_
     dst[i] = store_as<B>(load_as<float>(src[i]));
 }
 
+// copy between the active mesh and a local-smoothing level (Algorithm 1):
+// dst[di[q]] = src[si[q]], n_vec interleaved values per DoF
+template <typename A, typename B>
+__global__ void copy_map_kernel(int64_t n, int nv, const int32_t* __restrict__ si, const int32_t* __restrict__ di,
+                                const A* __restrict__ src, B* __restrict__ dst) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n * nv;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t q = t / nv;
+    const int64_t v = t - q * nv;
+    dst[static_cast<int64_t>(di[q]) * nv + v] = store_as<B>(load_as<double>(src[static_cast<int64_t>(si[q]) * nv + v]));
+  }
+}
+
+// refinement-edge DoFs of a local-smoothing level: zero inverse diagonal
+__global__ void zero_entries_kernel(int64_t n, const int32_t* __restrict__ idx, double* __restrict__ a64,
+                                    float* __restrict__ a32) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    a64[idx[t]] = 0.0;
+    a32[idx[t]] = 0.0f;
+  }
+}
+
 template <typename S>
 __global__ void acc_to_storage_kernel(int64_t n, const typename Acc<S>::type* __restrict__ src,
                                       S* __restrict__ dst) {
@@ -1624,6 +1647,38 @@ void launch_cast(int dtype_src, int dtype_dst, int64_t n, const void* src, void*
     (void)hipMemcpyAsync(dst, src, n * dtype_size(dtype_src), hipMemcpyDeviceToDevice, s);
   else
     throw Error(MFMG_ERR_UNSUPPORTED, "cast");
+  check_launch();
+}
+
+namespace {
+template <typename A>
+void copy_map_to(int dtype_dst, int64_t n, int nv, const int32_t* si, const int32_t* di, const A* src, void* dst,
+                 hipStream_t s) {
+  const unsigned g = grid_for(n * nv);
+  switch (dtype_dst) {
+    case MFMG_F64: copy_map_kernel<A, double><<<g, VEC_THREADS, 0, s>>>(n, nv, si, di, src, static_cast<double*>(dst)); break;
+    case MFMG_F32: copy_map_kernel<A, float><<<g, VEC_THREADS, 0, s>>>(n, nv, si, di, src, static_cast<float*>(dst)); break;
+    case MFMG_BF16: copy_map_kernel<A, bf16><<<g, VEC_THREADS, 0, s>>>(n, nv, si, di, src, static_cast<bf16*>(dst)); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+}
+}  // namespace
+
+void launch_copy_map(int dtype_src, int dtype_dst, int64_t n, int nv, const int32_t* src_idx, const int32_t* dst_idx,
+                     const void* src, void* dst, hipStream_t s) {
+  if (n == 0) return;
+  switch (dtype_src) {
+    case MFMG_F64: copy_map_to(dtype_dst, n, nv, src_idx, dst_idx, static_cast<const double*>(src), dst, s); break;
+    case MFMG_F32: copy_map_to(dtype_dst, n, nv, src_idx, dst_idx, static_cast<const float*>(src), dst, s); break;
+    case MFMG_BF16: copy_map_to(dtype_dst, n, nv, src_idx, dst_idx, static_cast<const bf16*>(src), dst, s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
+  check_launch();
+}
+
+void launch_zero_entries(int64_t n, const int32_t* idx, double* a64, float* a32, hipStream_t s) {
+  if (n == 0) return;
+  zero_entries_kernel<<<grid_for(n), VEC_THREADS, 0, s>>>(n, idx, a64, a32);
   check_launch();
 }
 

@@ -105,6 +105,11 @@ void launch_cast_to_f64(int dtype, int64_t n, const void* src, double* dst, hipS
 void launch_cast(int dtype_src, int dtype_dst, int64_t n, const void* src, void* dst, hipStream_t s);
 // acc -> S
 void launch_acc_to_storage(int dtype, int64_t n, const void* acc, void* dst, hipStream_t s);
+// dst[dst_idx[q]] = src[src_idx[q]] for q < n, n_vec interleaved values, with a cast
+void launch_copy_map(int dtype_src, int dtype_dst, int64_t n, int nv, const int32_t* src_idx, const int32_t* dst_idx,
+                     const void* src, void* dst, hipStream_t s);
+// a64[idx[q]] = a32[idx[q]] = 0 for q < n
+void launch_zero_entries(int64_t n, const int32_t* idx, double* a64, float* a32, hipStream_t s);
 // dinv = 1/diag in acc type (0 where diag == 0)
 void launch_inverse_diag(int dtype, int64_t n, const double* diag, void* dinv, hipStream_t s);
 // x (S) = Ainv (acc type, n0 x n0 row-major) b (S); nv interleaved vectors

@@ -84,6 +84,23 @@ std::vector<Cell> Octree::leaves() const {
   return out;
 }
 
+std::vector<Cell> Octree::cells_of_level(int l) const {
+  std::vector<Cell> out;
+  if (l == 0) {
+    for (int64_t k = 0; k < n0; ++k)
+      for (int64_t j = 0; j < n0; ++j)
+        for (int64_t i = 0; i < n0; ++i) out.push_back({0, i, j, k});
+    return out;
+  }
+  if (l < 1 || l - 1 >= n_levels()) return out;
+  for (uint64_t pk : refined[l - 1]) {
+    int64_t pi, pj, pkk;
+    unkey(pk, pi, pj, pkk);
+    for (int c = 0; c < 8; ++c) out.push_back({l, 2 * pi + (c & 1), 2 * pj + ((c >> 1) & 1), 2 * pkk + ((c >> 2) & 1)});
+  }
+  return out;
+}
+
 int64_t Octree::n_leaves() const {
   int64_t n = static_cast<int64_t>(n0) * n0 * n0;
   for (const auto& r : refined) n += 7 * static_cast<int64_t>(r.size());

@@ -61,6 +61,8 @@ class Octree {
 
   // leaves of every level
   std::vector<Cell> leaves() const;
+  // every cell of level l, refined or not
+  std::vector<Cell> cells_of_level(int l) const;
   int64_t n_leaves() const;
 
   void refine_where(int kind, const double* params);

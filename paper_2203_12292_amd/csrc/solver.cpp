@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <thread>
+#include <unordered_map>
 
 #include "context.hpp"
 #include "fe1d.hpp"
@@ -186,6 +187,166 @@ void upload_into(DeviceArray<T>& d, const std::vector<T>& h) { d.upload(h); }
 
 }  // namespace
 
+namespace {
+// Device data of one level from its host description; `work` allocates the
+// V-cycle work vectors.
+void init_level(Context& ctx, Level& L, const LevelDofs& H, double lo, bool work, hipStream_t s) {
+  L.n_dofs = H.n_dofs;
+  L.n_cells = H.n_cells;
+  L.n_hanging = H.n_hanging_cells;
+  L.ent.upload(H.ent);
+  L.mask.upload(H.mask);
+  std::vector<int32_t> ijk(3 * H.n_cells);
+  for (int64_t c = 0; c < H.n_cells; ++c) {
+    ijk[3 * c] = static_cast<int32_t>(H.cells[c].i);
+    ijk[3 * c + 1] = static_cast<int32_t>(H.cells[c].j);
+    ijk[3 * c + 2] = static_cast<int32_t>(H.cells[c].k);
+  }
+  L.ijk.upload(ijk);
+  L.host_ijk = ijk;
+  L.host_levels.resize(H.n_cells);
+  for (int64_t c = 0; c < H.n_cells; ++c) L.host_levels[c] = H.cells[c].level;
+  L.view.ent = L.ent.ptr;
+  L.view.mask = L.mask.ptr;
+  L.view.ijk = L.ijk.ptr;
+  L.view.n_cells = H.n_cells;
+  L.view.n_dofs = H.n_dofs;
+  L.view.n_shared = H.n_shared;
+  L.view.k = L.k;
+  L.view.h0 = H.h0;
+  L.view.lo = lo;
+  {
+    std::vector<CellMeta> meta(H.n_cells);
+    for (int64_t c = 0; c < H.n_cells; ++c) {
+      for (int sl = 0; sl < N_SLOTS; ++sl) meta[c].loc[sl] = H.loc[sl * H.n_cells + c];
+      meta[c].loc[27] = 0xffff;
+      meta[c].mask = H.mask[c];
+      meta[c].pad = 0;
+    }
+    L.meta.upload(meta);
+  }
+  L.batch_cell.upload(H.batch_cell_off);
+  L.batch_sh.upload(H.batch_sh_off);
+  L.batch_ex.upload(H.batch_ex_off);
+  L.sh_idx.upload(H.sh_idx);
+  L.red_idx.upload(H.red_idx);
+  L.red_off.upload(H.red_off);
+  L.partial.alloc(std::max<size_t>(1, H.sh_idx.size()) * ctx.max_rhs * 8);
+  L.view.n_batches = H.n_batches;
+  L.view.meta = L.meta.ptr;
+  L.view.batch_cell = L.batch_cell.ptr;
+  L.view.batch_sh = L.batch_sh.ptr;
+  L.view.batch_ex = L.batch_ex.ptr;
+  L.view.sh_idx = L.sh_idx.ptr;
+  L.view.red_idx = L.red_idx.ptr;
+  L.view.red_off = L.red_off.ptr;
+  L.view.partial = L.partial.ptr;
+  const int64_t nrhs = L.n_dofs * ctx.max_rhs;
+  const size_t sb = dtype_size(L.dtype);
+  if (work) {
+    L.x.alloc(nrhs * sb);
+    L.b.alloc(nrhs * sb);
+    L.r.alloc(nrhs * sb);
+    L.d.alloc(nrhs * 8);
+    L.tmp_cast.alloc(nrhs * 8);
+  }
+  L.t.alloc(nrhs * 8);
+  L.diag.alloc(L.n_dofs);
+  L.dinv.alloc(L.n_dofs * 8 * 2);  // double copy, then float copy
+  launch_diagonal(L.view, L.diag.ptr, s);
+  launch_inverse_diag(MFMG_F64, L.n_dofs, L.diag.ptr, L.dinv.ptr, s);
+  launch_inverse_diag(MFMG_F32, L.n_dofs, L.diag.ptr, L.dinv.ptr + L.n_dofs * 8, s);
+}
+
+void init_transfer(Level& L, const TransferDofs& T, bool poly) {
+  L.has_transfer = true;
+  L.tr_ident_c.upload(T.ident_coarse);
+  L.tr_ident_f.upload(T.ident_fine);
+  L.tr_ref_c.upload(T.refined_coarse);
+  L.tr_ref_f.upload(T.refined_fine);
+  L.tr_valence.upload(T.valence);
+  L.tview.polynomial = poly;
+  L.tview.ident_coarse = L.tr_ident_c.ptr;
+  L.tview.ident_fine = L.tr_ident_f.ptr;
+  L.tview.n_ident = static_cast<int64_t>(T.ident_coarse.size());
+  L.tview.refined_coarse = L.tr_ref_c.ptr;
+  L.tview.refined_fine = L.tr_ref_f.ptr;
+  L.tview.n_refined = static_cast<int64_t>(T.refined_coarse.size());
+  L.tview.valence = L.tr_valence.ptr;
+}
+
+int level_dtype(const mfmg_level_desc& desc, int l) {
+  const int dt = desc.n_level_dtype <= 0 ? MFMG_F64 : desc.level_dtype[std::min(l, desc.n_level_dtype - 1)];
+  MFMG_REQUIRE(dt >= MFMG_F64 && dt <= MFMG_BF16, MFMG_ERR_UNSUPPORTED, "level dtype");
+  return dt;
+}
+
+// Local smoothing (Section 2.1): one level per refinement level, holding all
+// of its cells; refinement-edge DoFs get a zero inverse diagonal, so that the
+// Chebyshev smoother acts on A_SS and keeps the edge values.  The copy maps
+// of Algorithm 1 pair the entities of the leaves of each level (interior
+// ones only) with the same entities of the active mesh.
+void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vector<LevelDofs>& host, hipStream_t s) {
+  MFMG_REQUIRE(desc.dirichlet != 0, MFMG_ERR_UNSUPPORTED, "local smoothing needs Dirichlet boundary conditions");
+  const Octree& tree = ctx.meshes.back();
+  std::vector<int> lv;
+  for (int l = 0; l <= tree.n_levels(); ++l)
+    if (l == 0 || (l - 1 < tree.n_levels() && !tree.refined[l - 1].empty())) lv.push_back(l);
+  MFMG_REQUIRE(lv.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
+  const int nl = static_cast<int>(lv.size());
+  ctx.ls = true;
+  ctx.levels.clear();
+  ctx.levels.resize(nl);
+  host.assign(nl, LevelDofs());
+  for (int l = 0; l < nl; ++l) {
+    Level& L = ctx.levels[l];
+    L.mesh = static_cast<int>(ctx.meshes.size()) - 1;
+    L.only_level = lv[l];
+    L.k = desc.degree;
+    L.dtype = level_dtype(desc, l);
+    MFMG_REQUIRE(L.dtype == ctx.levels[0].dtype, MFMG_ERR_UNSUPPORTED,
+                 "local smoothing needs one storage type on all levels");
+    host[l] = build_level_dofs(tree, L.k, true, false, lv[l]);
+    MFMG_REQUIRE(l > 0 || host[0].n_edge_dofs == 0, MFMG_ERR_INVALID_ARG, "the coarse grid has an edge");
+    init_level(ctx, L, host[l], tree.lo, true, s);
+    L.n_edge = host[l].n_edge_dofs;
+    L.host_edge = host[l].dof_edge;
+    std::vector<int32_t> edge;
+    edge.reserve(L.n_edge);
+    for (int64_t i = 0; i < L.n_dofs; ++i)
+      if (host[l].dof_edge[i]) edge.push_back(static_cast<int32_t>(i));
+    L.edge_idx.upload(edge);
+    launch_zero_entries(L.n_edge, L.edge_idx.ptr, reinterpret_cast<double*>(L.dinv.ptr),
+                        reinterpret_cast<float*>(L.dinv.ptr + L.n_dofs * 8), s);
+  }
+  for (int l = 1; l < nl; ++l) init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], false, true), false);
+  // the active mesh (the outer solver's operator), FP64
+  LevelDofs A = build_level_dofs(tree, desc.degree, true, false);
+  Level& F = ctx.active;
+  F.mesh = static_cast<int>(ctx.meshes.size()) - 1;
+  F.k = desc.degree;
+  F.dtype = MFMG_F64;
+  init_level(ctx, F, A, tree.lo, false, s);
+  // copy maps; every active DoF belongs to exactly one level
+  const EntityIndex index(A);
+  std::vector<uint8_t> covered(A.n_dofs, 0);
+  for (int l = 0; l < nl; ++l) {
+    std::vector<int32_t> cl, ca;
+    ls_copy_pairs(host[l], A, index, cl, ca);
+    for (int32_t a : ca) {
+      MFMG_REQUIRE(!covered[a], MFMG_ERR_INVALID_ARG, "copy map: active DoF on two levels");
+      covered[a] = 1;
+    }
+    Level& L = ctx.levels[l];
+    L.n_copy = static_cast<int64_t>(cl.size());
+    L.cp_level.upload(cl);
+    L.cp_active.upload(ca);
+  }
+  for (int64_t i = 0; i < A.n_dofs; ++i)
+    MFMG_REQUIRE(covered[i], MFMG_ERR_INVALID_ARG, "copy map: active DoF on no level");
+}
+}  // namespace
+
 void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc& desc, hipStream_t s) {
   MFMG_REQUIRE(desc.degree >= 1 && desc.degree <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   ctx.desc = desc;
@@ -197,104 +358,30 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   const double range = desc.smoothing_range > 0 ? desc.smoothing_range : 20.0;
   const double safety = desc.eig_safety > 0 ? desc.eig_safety : 1.2;
   const int eig_it = desc.eig_iterations > 0 ? desc.eig_iterations : 15;
-  const auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);
-  MFMG_REQUIRE(pairs.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
-  const int nl = static_cast<int>(pairs.size());
-  ctx.levels.clear();
-  ctx.levels.resize(nl);
-  std::vector<LevelDofs> host(nl);
-  for (int l = 0; l < nl; ++l) {
-    Level& L = ctx.levels[l];
-    L.mesh = pairs[l].first;
-    L.k = pairs[l].second;
-    if (desc.n_level_dtype <= 0) L.dtype = MFMG_F64;
-    else L.dtype = desc.level_dtype[std::min(l, desc.n_level_dtype - 1)];
-    MFMG_REQUIRE(L.dtype >= MFMG_F64 && L.dtype <= MFMG_BF16, MFMG_ERR_UNSUPPORTED, "level dtype");
-    host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false);
-    const LevelDofs& H = host[l];
-    L.n_dofs = H.n_dofs;
-    L.n_cells = H.n_cells;
-    L.n_hanging = H.n_hanging_cells;
-    L.ent.upload(H.ent);
-    L.mask.upload(H.mask);
-    std::vector<int32_t> ijk(3 * H.n_cells);
-    for (int64_t c = 0; c < H.n_cells; ++c) {
-      ijk[3 * c] = static_cast<int32_t>(H.cells[c].i);
-      ijk[3 * c + 1] = static_cast<int32_t>(H.cells[c].j);
-      ijk[3 * c + 2] = static_cast<int32_t>(H.cells[c].k);
+  std::vector<LevelDofs> host;
+  if (desc.scheme == MFMG_SCHEME_LS) {
+    setup_local_smoothing(ctx, desc, host, s);
+  } else {
+    const auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);
+    MFMG_REQUIRE(pairs.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
+    const int nl = static_cast<int>(pairs.size());
+    ctx.levels.clear();
+    ctx.levels.resize(nl);
+    host.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+      Level& L = ctx.levels[l];
+      L.mesh = pairs[l].first;
+      L.k = pairs[l].second;
+      L.dtype = level_dtype(desc, l);
+      host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false);
+      init_level(ctx, L, host[l], ctx.meshes[L.mesh].lo, true, s);
     }
-    L.ijk.upload(ijk);
-    L.host_ijk = ijk;
-    L.host_levels.resize(H.n_cells);
-    for (int64_t c = 0; c < H.n_cells; ++c) L.host_levels[c] = H.cells[c].level;
-    L.view.ent = L.ent.ptr;
-    L.view.mask = L.mask.ptr;
-    L.view.ijk = L.ijk.ptr;
-    L.view.n_cells = H.n_cells;
-    L.view.n_dofs = H.n_dofs;
-    L.view.n_shared = H.n_shared;
-    L.view.k = L.k;
-    L.view.h0 = H.h0;
-    L.view.lo = ctx.meshes[L.mesh].lo;
-    {
-      std::vector<CellMeta> meta(H.n_cells);
-      for (int64_t c = 0; c < H.n_cells; ++c) {
-        for (int sl = 0; sl < N_SLOTS; ++sl) meta[c].loc[sl] = H.loc[sl * H.n_cells + c];
-        meta[c].loc[27] = 0xffff;
-        meta[c].mask = H.mask[c];
-        meta[c].pad = 0;
-      }
-      L.meta.upload(meta);
+    for (int l = 1; l < nl; ++l) {
+      const bool poly = ctx.levels[l - 1].mesh == ctx.levels[l].mesh;
+      init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly), poly);
     }
-    L.batch_cell.upload(H.batch_cell_off);
-    L.batch_sh.upload(H.batch_sh_off);
-    L.batch_ex.upload(H.batch_ex_off);
-    L.sh_idx.upload(H.sh_idx);
-    L.red_idx.upload(H.red_idx);
-    L.red_off.upload(H.red_off);
-    L.partial.alloc(std::max<size_t>(1, H.sh_idx.size()) * ctx.max_rhs * 8);
-    L.view.n_batches = H.n_batches;
-    L.view.meta = L.meta.ptr;
-    L.view.batch_cell = L.batch_cell.ptr;
-    L.view.batch_sh = L.batch_sh.ptr;
-    L.view.batch_ex = L.batch_ex.ptr;
-    L.view.sh_idx = L.sh_idx.ptr;
-    L.view.red_idx = L.red_idx.ptr;
-    L.view.red_off = L.red_off.ptr;
-    L.view.partial = L.partial.ptr;
-    const int64_t nrhs = L.n_dofs * ctx.max_rhs;
-    const size_t sb = dtype_size(L.dtype);
-    L.x.alloc(nrhs * sb);
-    L.b.alloc(nrhs * sb);
-    L.r.alloc(nrhs * sb);
-    L.d.alloc(nrhs * 8);
-    L.t.alloc(nrhs * 8);
-    L.tmp_cast.alloc(nrhs * 8);
-    L.diag.alloc(L.n_dofs);
-    L.dinv.alloc(L.n_dofs * 8 * 2);  // double copy, then float copy
-    launch_diagonal(L.view, L.diag.ptr, s);
-    launch_inverse_diag(MFMG_F64, L.n_dofs, L.diag.ptr, L.dinv.ptr, s);
-    launch_inverse_diag(MFMG_F32, L.n_dofs, L.diag.ptr, L.dinv.ptr + L.n_dofs * 8, s);
   }
-  for (int l = 1; l < nl; ++l) {
-    Level& L = ctx.levels[l];
-    const bool poly = ctx.levels[l - 1].mesh == L.mesh;
-    TransferDofs T = build_transfer(host[l], host[l - 1], poly);
-    L.has_transfer = true;
-    L.tr_ident_c.upload(T.ident_coarse);
-    L.tr_ident_f.upload(T.ident_fine);
-    L.tr_ref_c.upload(T.refined_coarse);
-    L.tr_ref_f.upload(T.refined_fine);
-    L.tr_valence.upload(T.valence);
-    L.tview.polynomial = poly;
-    L.tview.ident_coarse = L.tr_ident_c.ptr;
-    L.tview.ident_fine = L.tr_ident_f.ptr;
-    L.tview.n_ident = static_cast<int64_t>(T.ident_coarse.size());
-    L.tview.refined_coarse = L.tr_ref_c.ptr;
-    L.tview.refined_fine = L.tr_ref_f.ptr;
-    L.tview.n_refined = static_cast<int64_t>(T.refined_coarse.size());
-    L.tview.valence = L.tr_valence.ptr;
-  }
+  const int nl = static_cast<int>(ctx.levels.size());
   sync(s);
   for (int l = 1; l < nl; ++l) estimate_eigenvalues(ctx, ctx.levels[l], eig_it, safety, range, s);
   // exact coarse solver
@@ -418,16 +505,12 @@ void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipSt
 }
 
 namespace {
+void coarse_level_solve(Context& ctx, int nv, hipStream_t s);
+
 void vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
   Level& L = ctx.levels[l];
   if (l == 0) {
-    NetState& N = ctx.net;
-    if (N.rec_count < N.rec_capacity && nv == 1) {
-      launch_cast(L.dtype, MFMG_F64, L.n_dofs, L.b.ptr, N.record.ptr + static_cast<int64_t>(N.rec_count) * L.n_dofs, s);
-      ++N.rec_count;
-    }
-    if (N.mode != MFMG_COARSE_EXACT && nv == 1) net_coarse_solve(ctx, L.dtype, L.x.ptr, L.b.ptr, s);
-    else coarse_solve(ctx, L.dtype, nv, L.x.ptr, L.b.ptr, s);
+    coarse_level_solve(ctx, nv, s);
     return;
   }
   Level& C = ctx.levels[l - 1];
@@ -457,8 +540,75 @@ void vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+void coarse_level_solve(Context& ctx, int nv, hipStream_t s) {
+  Level& L = ctx.levels[0];
+  NetState& N = ctx.net;
+  if (N.rec_count < N.rec_capacity && nv == 1) {
+    launch_cast(L.dtype, MFMG_F64, L.n_dofs, L.b.ptr, N.record.ptr + static_cast<int64_t>(N.rec_count) * L.n_dofs, s);
+    ++N.rec_count;
+  }
+  if (N.mode != MFMG_COARSE_EXACT && nv == 1) net_coarse_solve(ctx, L.dtype, L.x.ptr, L.b.ptr, s);
+  else coarse_solve(ctx, L.dtype, nv, L.x.ptr, L.b.ptr, s);
+}
+
+// Algorithm 2, local-smoothing branch.  The edge DoFs have a zero inverse
+// diagonal: presmoothing from x = 0 leaves x_E = 0, so the residual gives
+// b_S - A_SS x_S on interior DoFs and -A_ES x_S on edge DoFs (b_E is 0: the
+// copy to the levels writes interior DoFs only, and no refined cell of a
+// level touches its edge on a one-irregular mesh).  The restriction adds to
+// the coarser right-hand side, which already holds that level's share of the
+// copied b.  The prolongation also sets x_E; the postsmoother's operator then
+// applies A_SS x_S + A_SE x_E while it keeps x_E, which is the edge step
+// b_S - A_SE x_E folded into the smoother.
+void ls_vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
+  if (l == 0) {
+    coarse_level_solve(ctx, nv, s);
+    return;
+  }
+  Level& L = ctx.levels[l];
+  Level& C = ctx.levels[l - 1];
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, true, L.lmin, L.lmax, s);
+  level_residual(ctx, l, nv, L.r.ptr, L.b.ptr, L.x.ptr, s);
+  level_restrict_add(ctx, l, L.dtype, nv, C.b.ptr, L.r.ptr, s);
+  ls_vcycle_level(ctx, l - 1, nv, s);
+  level_prolongate_add(ctx, l, L.dtype, nv, L.x.ptr, C.x.ptr, s);
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, false, L.lmin, L.lmax, s);
+}
+}  // namespace
+
+void copy_to_mg(Context& ctx, int l, int nv, void* dst, const double* src, hipStream_t s) {
+  Level& L = ctx.level(l);
+  if (!ctx.ls) {
+    MFMG_REQUIRE(&L == &ctx.levels.back(), MFMG_ERR_INVALID_ARG, "copy to the levels: finest level only");
+    launch_cast(MFMG_F64, L.dtype, L.n_dofs * nv, src, dst, s);
+    return;
+  }
+  MFMG_REQUIRE(&L != &ctx.active, MFMG_ERR_INVALID_ARG, "copy to the levels: not a multigrid level");
+  launch_fill(0, dst, L.n_dofs * nv * static_cast<int64_t>(dtype_size(L.dtype)), s);
+  launch_copy_map(MFMG_F64, L.dtype, L.n_copy, nv, L.cp_active.ptr, L.cp_level.ptr, src, dst, s);
+}
+
+void copy_from_mg(Context& ctx, int l, int nv, double* dst, const void* src, hipStream_t s) {
+  Level& L = ctx.level(l);
+  if (!ctx.ls) {
+    MFMG_REQUIRE(&L == &ctx.levels.back(), MFMG_ERR_INVALID_ARG, "copy from the levels: finest level only");
+    launch_cast(L.dtype, MFMG_F64, L.n_dofs * nv, src, dst, s);
+    return;
+  }
+  MFMG_REQUIRE(&L != &ctx.active, MFMG_ERR_INVALID_ARG, "copy from the levels: not a multigrid level");
+  launch_copy_map(L.dtype, MFMG_F64, L.n_copy, nv, L.cp_level.ptr, L.cp_active.ptr, src, dst, s);
+}
+
 void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s) {
   MFMG_REQUIRE(nv >= 1 && nv <= ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+  if (ctx.ls) {  // Algorithm 1 over all levels, then the local-smoothing cycle
+    const int nl = static_cast<int>(ctx.levels.size());
+    for (int l = 0; l < nl; ++l) copy_to_mg(ctx, l, nv, ctx.levels[l].b.ptr, b, s);
+    ls_vcycle_level(ctx, nl - 1, nv, s);
+    for (int l = 0; l < nl; ++l) copy_from_mg(ctx, l, nv, x, ctx.levels[l].x.ptr, s);
+    return;
+  }
   Level& F = ctx.fine();
   const int64_t n = F.n_dofs * nv;
   launch_cast(MFMG_F64, F.dtype, n, b, F.b.ptr, s);  // copy_to_mg

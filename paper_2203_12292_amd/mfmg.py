@@ -20,7 +20,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: 
 (ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN,
  ERR_NET_REJECTED) = -1, -2, -3, -4, -5, -6, -7
 F64, F32, BF16 = 0, 1, 2
-SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P = 0, 1, 2
+SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P, SCHEME_LS = 0, 1, 2, 3
+LEVEL_ACTIVE = -1  # the leaves (the outer solver's mesh)
 RHS_CONST, RHS_GAUSS, RHS_SINE = 0, 1, 2
 COARSE_EXACT, COARSE_LEARNED, COARSE_ZERO = 0, 1, 2
 MAX_STEPS, MAX_LEVELS = 16, 32
@@ -65,6 +66,8 @@ _SIGS = {
     "mfmg_setup_mesh": (_I, [C.POINTER(MeshDesc), C.POINTER(_P)]),
     "mfmg_mesh_info": (_I, [_P, C.POINTER(_I), _I64P, _I64P]),
     "mfmg_host_level_matrix": (_I, [_P, _I, _I, _I, _I64P, _I64P, C.POINTER(C.c_double)]),
+    "mfmg_host_ls_level": (_I, [_P, _I, _I, _I64P, _I64P, _I64P, C.POINTER(C.c_uint8), C.POINTER(C.c_double),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mfmg_setup_levels": (_I, [_P, C.POINTER(LevelDesc), _P, C.POINTER(_P)]),
     "mfmg_n_levels": (_I, [_P, C.POINTER(_I)]),
     "mfmg_level_info": (_I, [_P, _I, _I64P, _I64P, C.POINTER(_I), C.POINTER(_I), _I64P]),
@@ -78,6 +81,9 @@ _SIGS = {
     "mfmg_restrict_add": (_I, [_P, _I, _I, _I, _P, _P, _P]),
     "mfmg_coarse_solve": (_I, [_P, _I, _I, _P, _P, _P]),
     "mfmg_vcycle": (_I, [_P, _I, _P, _P, _P]),
+    "mfmg_copy_to_mg": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mfmg_copy_from_mg": (_I, [_P, _I, _I, _P, _P, _P]),
+    "mfmg_level_edge": (_I, [_P, _I, _I64P, C.POINTER(C.c_uint8)]),
     "mfmg_solve": (_I, [_P, _I, _P, _P, C.c_double, _I, _I, C.POINTER(SolveStats), _P]),
     "mfmg_rhs": (_I, [_P, _I, _I, C.POINTER(C.c_double), _I, _I, _P, _P]),
     "mfmg_distribute": (_I, [_P, _I, _P, _P, _P]),
@@ -171,6 +177,25 @@ class Mesh:
             A.ctypes.data_as(C.POINTER(C.c_double)) if dense else None))
         return codes, A
 
+    def host_ls_level(self, level, degree, dense=False):
+        """Local-smoothing level from the host set-up: dict of codes (n,3),
+        edge flags, dense matrix (or None), and the copy map (level DoFs,
+        active DoFs)."""
+        n, m = C.c_int64(), C.c_int64()
+        _check(lib().mfmg_host_ls_level(self.handle, level, degree, C.byref(n), C.byref(m), None, None, None, None,
+                                        None))
+        codes = np.zeros((n.value, 3), dtype=np.int64)
+        edge = np.zeros(n.value, dtype=np.uint8)
+        A = np.zeros((n.value, n.value)) if dense else None
+        cl = np.zeros(m.value, dtype=np.int32)
+        ca = np.zeros(m.value, dtype=np.int32)
+        _check(lib().mfmg_host_ls_level(
+            self.handle, level, degree, C.byref(n), C.byref(m), codes.ctypes.data_as(_I64P),
+            edge.ctypes.data_as(C.POINTER(C.c_uint8)),
+            A.ctypes.data_as(C.POINTER(C.c_double)) if dense else None,
+            cl.ctypes.data_as(C.POINTER(C.c_int32)), ca.ctypes.data_as(C.POINTER(C.c_int32))))
+        return {"codes": codes, "edge": edge.astype(bool), "dense": A, "copy_level": cl, "copy_active": ca}
+
     def close(self):
         if self.handle:
             lib().mfmg_destroy_mesh(self.handle)
@@ -213,8 +238,15 @@ class Solver:
         return {"n_dofs": nd.value, "n_cells": nc.value, "degree": k.value, "dtype": dt.value,
                 "n_hanging_cells": nh.value}
 
-    def n_dofs(self, level=None):
-        return self.level_info(self.n_levels - 1 if level is None else level)["n_dofs"]
+    def n_dofs(self, level=LEVEL_ACTIVE):
+        return self.level_info(level)["n_dofs"]
+
+    def level_edge(self, level):
+        """(number of refinement-edge DoFs, uint8 flag per DoF) of a level."""
+        n = C.c_int64()
+        flags = np.zeros(self.n_dofs(level), dtype=np.uint8)
+        _check(lib().mfmg_level_edge(self.handle, level, C.byref(n), flags.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return n.value, flags
 
     def dof_codes(self, level):
         n = self.n_dofs(level)
@@ -261,6 +293,14 @@ class Solver:
         _check(lib().mfmg_coarse_solve(self.handle, _dtype_code(x), n_vec, _ptr(x), _ptr(b), _stream()))
         return x
 
+    def copy_to_mg(self, level, dst, src, n_vec=1):
+        _check(lib().mfmg_copy_to_mg(self.handle, level, n_vec, _ptr(dst), _ptr(src), _stream()))
+        return dst
+
+    def copy_from_mg(self, level, dst, src, n_vec=1):
+        _check(lib().mfmg_copy_from_mg(self.handle, level, n_vec, _ptr(dst), _ptr(src), _stream()))
+        return dst
+
     def vcycle(self, x, b, n_vec=1):
         _check(lib().mfmg_vcycle(self.handle, n_vec, _ptr(x), _ptr(b), _stream()))
         return x
@@ -277,15 +317,13 @@ class Solver:
                 "time_ms": st.time_ms, "history": hist, "coarse_fallbacks": st.coarse_fallbacks,
                 "coarse_accepted": st.coarse_accepted}
 
-    def rhs(self, b, kind=RHS_CONST, params=(1.0,), n_terms=0, n_vec=1, level=None):
-        level = self.n_levels - 1 if level is None else level
+    def rhs(self, b, kind=RHS_CONST, params=(1.0,), n_terms=0, n_vec=1, level=LEVEL_ACTIVE):
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
         _check(lib().mfmg_rhs(self.handle, level, kind, p.ctypes.data_as(C.POINTER(C.c_double)), n_terms, n_vec,
                               _ptr(b), _stream()))
         return b
 
-    def distribute(self, x, out, level=None):
-        level = self.n_levels - 1 if level is None else level
+    def distribute(self, x, out, level=LEVEL_ACTIVE):
         _check(lib().mfmg_distribute(self.handle, level, _ptr(x), _ptr(out), _stream()))
         return out
 

@@ -88,3 +88,26 @@ def test_host_codes_without_dirichlet():
     perm = perm_from_codes(S.codes_array(), codes)
     Ao = assemble_stiffness(S).toarray()
     assert np.abs(A[np.ix_(perm, perm)] - Ao).max() <= 1e-13 * np.abs(Ao).max()
+
+
+@pytest.mark.parametrize("name,k", [("tiny", 1), ("tiny", 2), ("small_m1", 3), ("small", 4)])
+def test_host_local_smoothing_levels_match_oracle(name, k):
+    """Each local-smoothing level of the library (host set-up): same DoFs,
+    refinement-edge flags, level matrix (edge rows included) and copy map as
+    the oracle's (Section 2.1; Algorithm 1)."""
+    from helpers import DESCS, oracle_tree
+    from oracle.local_smoothing import LSHierarchy
+    H = LSHierarchy(oracle_tree(name), k)
+    M = mfmg.Mesh(DESCS[name])
+    acodes, _ = M.host_level(len(M.info()[0]) - 1, k)
+    pa = perm_from_codes(H.active.codes_array(), acodes)
+    for L, V in zip(H.levels, H.spaces):
+        d = M.host_ls_level(V.level, k, dense=True)
+        p = perm_from_codes(V.codes_array(), d["codes"])
+        assert len(d["codes"]) == V.n_dofs
+        assert np.array_equal(d["edge"][p], V.edge), V.level
+        A = L.A_full.toarray()
+        assert np.abs(d["dense"][np.ix_(p, p)] - A).max() <= 1e-13 * np.abs(A).max(), V.level
+        lv, ac = H.maps[V.level]
+        assert sorted(zip(p[lv].tolist(), pa[ac].tolist())) == \
+            sorted(zip(d["copy_level"].tolist(), d["copy_active"].tolist())), V.level
