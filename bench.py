@@ -213,6 +213,14 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
     return "\n".join(lines)
 
 
+class _Progress(dict):
+    """Result dict that reports each finished stage on stderr."""
+
+    def __setitem__(self, key, value):
+        super().__setitem__(key, value)
+        print(f"[bench] {key}: {json.dumps(value)[:200]}", file=sys.stderr, flush=True)
+
+
 def _events_time(fn, k, stream):
     import torch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
@@ -355,8 +363,9 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
     }
 
+    print(f"[bench] operator: {avg_ms:.3f} ms per application, {value:.3e} DoFs/s", file=sys.stderr, flush=True)
     if not args.skip_solves:
-        solves = {}
+        solves = _Progress()
         b = torch.zeros(n, dtype=torch.float64, device=dev)
         solver.rhs(b)
         xs = torch.zeros_like(b)
@@ -372,6 +381,19 @@ def main():
         solves["cube16_q4_fp32_vcycle"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                                            "residual": st["final_residual"]}
         del s32
+        # geometric local smoothing (Section 2.1, the paper's comparison method) on
+        # the same problem: refinement-level levels down to the 16^3 coarse grid,
+        # then polynomial levels there as in the global-coarsening runs
+        for name, dts in (("cube16_q4_ls_fp64", []), ("cube16_q4_ls_fp32_vcycle", [mfmg.F32])):
+            torch.cuda.empty_cache()
+            t0 = time.time()
+            sls = mfmg.Solver(mesh, k, mfmg.SCHEME_LS_THEN_P, level_dtypes=dts)
+            setup_ls = time.time() - t0
+            for _ in range(2):
+                st = sls.solve(xs, b, rtol=1e-10, max_it=100, flexible=bool(dts))
+            solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                            "residual": st["final_residual"], "levels": sls.n_levels, "setup_s": round(setup_ls, 2)}
+            del sls
         m1 = mfmg.Mesh(synth.CFG1)
         for name, dts in (("cube4_q2_fp64", []), ("cube4_q2_mixed_bf16", [mfmg.BF16, mfmg.BF16, mfmg.F32])):
             s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, level_dtypes=dts)
@@ -382,6 +404,15 @@ def main():
                 st = s1.solve(x1, b1, rtol=1e-10, max_it=100, flexible=bool(dts))
             solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                             "residual": st["final_residual"]}
+        s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_LS)
+        b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
+        s1.rhs(b1)
+        x1 = torch.zeros_like(b1)
+        for _ in range(3):
+            st = s1.solve(x1, b1, rtol=1e-10, max_it=100)
+        solves["cube4_q2_ls_fp64"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                                      "residual": st["final_residual"]}
+        del s1
         # learned coarse correction (Q2 coarse grid, 343 DoFs)
         s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H)
         b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
@@ -432,7 +463,7 @@ def main():
             "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
             "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}
         del s4
-        out["time_to_solve"] = solves
+        out["time_to_solve"] = dict(solves)
 
     if not args.skip_cpu_baseline:
         dt, passes, n_sample, n_total = cpu_baseline(desc, k)

@@ -89,8 +89,13 @@ typedef struct {
  *           of Algorithm 2 and the copy to and from the levels of
  *           Algorithm 1; the outer solver works on the leaves (the active
  *           mesh, level index MFMG_LEVEL_ACTIVE).  Needs dirichlet = 1 and
- *           one storage type for all levels. */
-enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2, MFMG_SCHEME_LS = 3 };
+ *           one storage type for all levels.
+ *  LS_THEN_P local smoothing down to the coarse grid, then polynomial
+ *           coarsening on the coarse grid (levels 0 .. P-1 have degrees
+ *           1, 2, ..., floor(k/2); they cover the domain, have no edge and
+ *           receive no copied right-hand side). */
+enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2, MFMG_SCHEME_LS = 3,
+       MFMG_SCHEME_LS_THEN_P = 4 };
 
 /* Level index of the active mesh (the leaves) in every call that takes a
  * level: the finest level under global coarsening, the operator of the leaves

@@ -34,7 +34,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fe, solvers
+from . import fe, octree, solvers
+from .hierarchy import degree_sequence
 from .octree import _unpack3, pack
 from .space import Space, assemble_stiffness, prolongation
 
@@ -145,8 +146,9 @@ class LSLevel:
     def __init__(self, space, P, degree):
         self.space = space
         self.A_full = assemble_stiffness(space).tocsr()
-        self.S = np.flatnonzero(~space.edge)
-        self.E = np.flatnonzero(space.edge)
+        edge = getattr(space, "edge", np.zeros(space.n_dofs, bool))  # polynomial levels: no edge
+        self.S = np.flatnonzero(~edge)
+        self.E = np.flatnonzero(edge)
         self.smoother = solvers.Level(self.A_full[self.S][:, self.S], None, degree)
         self.A_ES = self.A_full[self.E][:, self.S]
         self.A_SE = self.A_full[self.S][:, self.E]
@@ -155,12 +157,21 @@ class LSLevel:
 
 
 class LSHierarchy:
-    """Local-smoothing multigrid for the Q_k problem on the leaves of ``tree``."""
+    """Local-smoothing multigrid for the Q_k problem on the leaves of ``tree``.
 
-    def __init__(self, tree, k, cheb_degree=3):
+    With ``coarse_p`` the coarse grid at degree k is followed by polynomial
+    levels on the coarse grid, k -> floor(k/2) -> ... -> 1 (Section 2.3), and
+    the direct solve happens at degree 1; these levels cover the domain and
+    have no refinement edge and no share of the copied right-hand side.
+    """
+
+    def __init__(self, tree, k, cheb_degree=3, coarse_p=False):
         self.active = Space(tree, k)
         self.A = assemble_stiffness(self.active)
         self.spaces = [LevelSpace(tree, l, k) for l in level_numbers(tree)]
+        if coarse_p:
+            grid = octree.gc_sequence(tree)[-1]
+            self.spaces = [Space(grid, d) for d in degree_sequence(k)[:0:-1]] + self.spaces
         self.levels = []
         for l, V in enumerate(self.spaces):
             P = prolongation(V, self.spaces[l - 1]) if l > 0 else None
@@ -169,7 +180,10 @@ class LSHierarchy:
         for L in self.levels[1:]:
             L.smoother.setup_smoother()
         self.coarse = solvers.CoarseDirect(self.levels[0].A_full)
-        self.maps = copy_maps(self.active, self.spaces)
+        ls_spaces = [V for V in self.spaces if isinstance(V, LevelSpace)]
+        ls_maps = dict(zip([V.level for V in ls_spaces], copy_maps(self.active, ls_spaces)))
+        empty = (np.zeros(0, np.int64), np.zeros(0, np.int64))
+        self.maps = [ls_maps[V.level] if isinstance(V, LevelSpace) else empty for V in self.spaces]
 
     # -- Algorithm 1 -----------------------------------------------------------------
     def copy_to_mg(self, b):

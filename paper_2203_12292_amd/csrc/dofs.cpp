@@ -511,6 +511,8 @@ void ls_copy_pairs(const LevelDofs& H, const LevelDofs& A, const EntityIndex& in
                    std::vector<int32_t>& ca) {
   cl.clear();
   ca.clear();
+  MFMG_REQUIRE(H.ent_on_leaf.size() == H.ent_key.size() && H.ent_edge.size() == H.ent_key.size(),
+               MFMG_ERR_INVALID_ARG, "copy map: not a local-smoothing level");
   for (size_t e = 0; e < H.ent_key.size(); ++e) {
     if (H.ent_first[e] < 0 || !H.ent_on_leaf[e] || H.ent_edge[e]) continue;
     auto it = index.by_key.find(H.ent_key[e]);

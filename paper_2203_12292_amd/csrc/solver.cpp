@@ -292,34 +292,45 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
   std::vector<int> lv;
   for (int l = 0; l <= tree.n_levels(); ++l)
     if (l == 0 || (l - 1 < tree.n_levels() && !tree.refined[l - 1].empty())) lv.push_back(l);
-  MFMG_REQUIRE(lv.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
-  const int nl = static_cast<int>(lv.size());
+  // LS_THEN_P: polynomial levels on the coarse grid below it (degrees 1, 2,
+  // ..., floor(k/2); Section 2.3), without edge or copied right-hand side
+  std::vector<int> pdeg;
+  if (desc.scheme == MFMG_SCHEME_LS_THEN_P)
+    for (int d = desc.degree / 2; d >= 1; d /= 2) pdeg.insert(pdeg.begin(), d);
+  const int np = static_cast<int>(pdeg.size());
+  MFMG_REQUIRE(lv.size() + np <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
+  const int nl = static_cast<int>(lv.size()) + np;
   ctx.ls = true;
   ctx.levels.clear();
   ctx.levels.resize(nl);
   host.assign(nl, LevelDofs());
   for (int l = 0; l < nl; ++l) {
     Level& L = ctx.levels[l];
-    L.mesh = static_cast<int>(ctx.meshes.size()) - 1;
-    L.only_level = lv[l];
-    L.k = desc.degree;
+    const bool poly_level = l < np;
+    L.mesh = poly_level ? 0 : static_cast<int>(ctx.meshes.size()) - 1;
+    L.only_level = poly_level ? -1 : lv[l - np];
+    L.k = poly_level ? pdeg[l] : desc.degree;
     L.dtype = level_dtype(desc, l);
     MFMG_REQUIRE(L.dtype == ctx.levels[0].dtype, MFMG_ERR_UNSUPPORTED,
                  "local smoothing needs one storage type on all levels");
-    host[l] = build_level_dofs(tree, L.k, true, false, lv[l]);
-    MFMG_REQUIRE(l > 0 || host[0].n_edge_dofs == 0, MFMG_ERR_INVALID_ARG, "the coarse grid has an edge");
+    host[l] = poly_level ? build_level_dofs(ctx.meshes[0], L.k, true, false)
+                         : build_level_dofs(tree, L.k, true, false, L.only_level);
+    MFMG_REQUIRE(l > np || host[l].n_edge_dofs == 0, MFMG_ERR_INVALID_ARG, "the coarse grid has an edge");
     init_level(ctx, L, host[l], tree.lo, true, s);
     L.n_edge = host[l].n_edge_dofs;
     L.host_edge = host[l].dof_edge;
     std::vector<int32_t> edge;
     edge.reserve(L.n_edge);
-    for (int64_t i = 0; i < L.n_dofs; ++i)
+    for (size_t i = 0; i < host[l].dof_edge.size(); ++i)
       if (host[l].dof_edge[i]) edge.push_back(static_cast<int32_t>(i));
     L.edge_idx.upload(edge);
     launch_zero_entries(L.n_edge, L.edge_idx.ptr, reinterpret_cast<double*>(L.dinv.ptr),
                         reinterpret_cast<float*>(L.dinv.ptr + L.n_dofs * 8), s);
   }
-  for (int l = 1; l < nl; ++l) init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], false, true), false);
+  for (int l = 1; l < nl; ++l) {
+    const bool poly = ctx.levels[l - 1].k != ctx.levels[l].k;
+    init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly, !poly), poly);
+  }
   // the active mesh (the outer solver's operator), FP64
   LevelDofs A = build_level_dofs(tree, desc.degree, true, false);
   Level& F = ctx.active;
@@ -330,7 +341,7 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
   // copy maps; every active DoF belongs to exactly one level
   const EntityIndex index(A);
   std::vector<uint8_t> covered(A.n_dofs, 0);
-  for (int l = 0; l < nl; ++l) {
+  for (int l = np; l < nl; ++l) {
     std::vector<int32_t> cl, ca;
     ls_copy_pairs(host[l], A, index, cl, ca);
     for (int32_t a : ca) {
@@ -359,7 +370,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   const double safety = desc.eig_safety > 0 ? desc.eig_safety : 1.2;
   const int eig_it = desc.eig_iterations > 0 ? desc.eig_iterations : 15;
   std::vector<LevelDofs> host;
-  if (desc.scheme == MFMG_SCHEME_LS) {
+  if (desc.scheme == MFMG_SCHEME_LS || desc.scheme == MFMG_SCHEME_LS_THEN_P) {
     setup_local_smoothing(ctx, desc, host, s);
   } else {
     const auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);

@@ -20,7 +20,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: 
 (ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN,
  ERR_NET_REJECTED) = -1, -2, -3, -4, -5, -6, -7
 F64, F32, BF16 = 0, 1, 2
-SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P, SCHEME_LS = 0, 1, 2, 3
+SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P, SCHEME_LS, SCHEME_LS_THEN_P = 0, 1, 2, 3, 4
 LEVEL_ACTIVE = -1  # the leaves (the outer solver's mesh)
 RHS_CONST, RHS_GAUSS, RHS_SINE = 0, 1, 2
 COARSE_EXACT, COARSE_LEARNED, COARSE_ZERO = 0, 1, 2

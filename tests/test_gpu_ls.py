@@ -31,10 +31,11 @@ def oracle_ls(name, k):
 
 
 @functools.lru_cache(maxsize=None)
-def gpu_ls(name, k, dtypes=()):
+def gpu_ls(name, k, dtypes=(), coarse_p=False):
     from paper_2203_12292_amd import mfmg
-    print(f"[setup] local smoothing mesh={name} k={k} dtypes={dtypes}", flush=True)
-    return mfmg.Solver(mfmg.Mesh(DESCS[name]), k, mfmg.SCHEME_LS, level_dtypes=list(dtypes))
+    print(f"[setup] local smoothing mesh={name} k={k} dtypes={dtypes} coarse_p={coarse_p}", flush=True)
+    return mfmg.Solver(mfmg.Mesh(DESCS[name]), k, mfmg.SCHEME_LS_THEN_P if coarse_p else mfmg.SCHEME_LS,
+                       level_dtypes=list(dtypes))
 
 
 @functools.lru_cache(maxsize=None)
@@ -207,3 +208,31 @@ def test_active_level_has_no_smoother():
     with pytest.raises(mfmg.MfmgError) as e:
         S.smooth(mfmg.LEVEL_ACTIVE, x, x.clone())
     assert e.value.code == mfmg.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name,k", [("tiny", 2), ("small", 4)])
+def test_vcycle_with_polynomial_coarse_levels(name, k):
+    """Local smoothing down to the coarse grid, then polynomial levels there
+    (degrees 1, 2, ..., floor(k/2)): V-cycle parity and the FP64 solve."""
+    H = LSHierarchy(oracle_tree(name), k, coarse_p=True)
+    S = gpu_ls(name, k, coarse_p=True)
+    assert S.n_levels == len(H.levels)
+    for l in range(S.n_levels):
+        assert S.level_info(l)["degree"] == H.levels[l].space.k
+    for l in range(1, S.n_levels):
+        H.levels[l].smoother.lmin, H.levels[l].smoother.lmax = S.smoother_range(l)
+    PA = perm_from_codes(H.active.codes_array(), S.dof_codes(-1))
+    b = np.random.default_rng(2).uniform(-1, 1, H.A.shape[0])
+    xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+    S.vcycle(xg, to_gpu(b, PA))
+    bg = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
+    S.rhs(bg)
+    xs = torch.zeros_like(bg)
+    st = S.solve(xs, bg, rtol=1e-12, max_it=80)
+    torch.cuda.synchronize()
+    assert rel_err(from_gpu(xg, PA), H.vcycle(b)) < 1e-11
+    b_o = assemble_load(H.active, constant(1.0))
+    xo = solvers.direct_solve(H.A, b_o)
+    err = np.linalg.norm(from_gpu(xs, PA) - xo) / np.linalg.norm(xo)
+    print(f"[ls+p solve] {name} k={k}: {st['iterations']} it, err {err:.2e}", flush=True)
+    assert st["converged"] and err < 1e-10

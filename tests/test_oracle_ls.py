@@ -181,3 +181,20 @@ def test_pcg_reaches_direct_solution_with_few_more_iterations_than_gc(name, k):
     xd = solvers.direct_solve(H.A, b)
     assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
     assert it_gc <= it_ls <= it_gc + 3, (it_ls, it_gc)
+
+
+@pytest.mark.parametrize("name,k", [("tiny", 2), ("small", 4)])
+def test_polynomial_coarse_levels_variant(name, k):
+    """Local smoothing down to the coarse grid, then polynomial coarsening
+    there: still a symmetric positive definite preconditioner, and PCG with it
+    reaches the direct solution."""
+    H = LSHierarchy(oracle_tree(name), k, coarse_p=True)
+    assert [L.space.k for L in H.levels[:2]] == [1, 2]
+    rng = np.random.default_rng(13)
+    u, v = rng.standard_normal(H.A.shape[0]), rng.standard_normal(H.A.shape[0])
+    Bu, Bv = H.vcycle(u), H.vcycle(v)
+    assert abs(u @ Bv - v @ Bu) <= 1e-12 * abs(u @ Bv) and u @ Bu > 0
+    b = assemble_load(H.active, constant(1.0))
+    x, it, _ = H.solve(b, rtol=1e-10)
+    xd = solvers.direct_solve(H.A, b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd) and it <= 20
