@@ -185,3 +185,35 @@ def test_transfers_full_size_galerkin_and_duality(name):
               f"duality {abs(d_f - d_c) / scale:.1e}", flush=True)
         assert abs(e_f - e_c) <= 1e-11 * abs(e_c), l
         assert abs(d_f - d_c) <= 1e-12 * scale, l
+
+
+def test_local_smoothing_full_size_q4():
+    """Local smoothing (refinement-level levels, then polynomial levels on the
+    16^3 coarse grid) on the 68M-DoF mesh: the copy to and from the levels
+    is a bijection onto the active DoFs, and the FP64 solve reaches 1e-10,
+    recomputed with the active operator (the same operator and numbering as
+    the sample-verified finest global-coarsening level)."""
+    from paper_2203_12292_amd import mfmg
+    print("[setup] cube16_ball4_q4 local smoothing", flush=True)
+    S = mfmg.Solver(mfmg.Mesh(synth.CFG2), 4, mfmg.SCHEME_LS_THEN_P)
+    n = S.n_dofs()
+    G = workload("cube16_ball4_q4")[0]
+    assert n == G.n_dofs() and np.array_equal(S.dof_codes(-1), workload("cube16_ball4_q4")[2])
+    v = torch.arange(n, dtype=torch.float64, device=DEV) + 1.0
+    back = torch.zeros_like(v)
+    for l in range(S.n_levels):
+        t = torch.empty(S.n_dofs(l), dtype=torch.float64, device=DEV)
+        S.copy_to_mg(l, t, v)
+        S.copy_from_mg(l, back, t)
+    torch.cuda.synchronize()
+    assert torch.equal(back, v)
+    b = torch.zeros(n, dtype=torch.float64, device=DEV)
+    S.rhs(b)
+    x = torch.zeros_like(b)
+    st = S.solve(x, b, rtol=1e-10, max_it=100)
+    r = torch.empty_like(b)
+    S.vmult(mfmg.LEVEL_ACTIVE, r, x)
+    res = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
+    print(f"[ls solve] {S.n_levels} levels, {st['iterations']} it, recomputed residual {res:.2e}", flush=True)
+    assert st["converged"] and res < 1.05e-10 and 3 <= st["iterations"] <= 30
+    S.close()
