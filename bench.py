@@ -394,7 +394,29 @@ def main():
             solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                             "residual": st["final_residual"], "levels": sls.n_levels, "setup_s": round(setup_ls, 2)}
             del sls
+        # geometric and polynomial coarsening in one step (Q4 -> Q2 -> Q1 with the mesh)
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        shp = mfmg.Solver(mesh, k, mfmg.SCHEME_HP)
+        setup_hp = time.time() - t0
+        for _ in range(2):
+            st = shp.solve(xs, b, rtol=1e-10, max_it=100)
+        solves["cube16_q4_hp_fp64"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                                       "residual": st["final_residual"], "levels": shp.n_levels,
+                                       "setup_s": round(setup_hp, 2)}
+        del shp
         m1 = mfmg.Mesh(synth.CFG1)
+        for drop in (1, 2):  # early switch to the coarse solver, on a level with hanging nodes
+            s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, drop_coarse=drop)
+            b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
+            s1.rhs(b1)
+            x1 = torch.zeros_like(b1)
+            for _ in range(3):
+                st = s1.solve(x1, b1, rtol=1e-10, max_it=100)
+            solves[f"cube4_q2_fp64_coarse_switch_{drop}"] = {
+                "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
+                "levels": s1.n_levels, "coarse_dofs": s1.n_dofs(0)}
+            del s1
         for name, dts in (("cube4_q2_fp64", []), ("cube4_q2_mixed_bf16", [mfmg.BF16, mfmg.BF16, mfmg.F32])):
             s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, level_dtypes=dts)
             b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
@@ -460,6 +482,16 @@ def main():
         x4 = torch.zeros_like(b4)
         st = s4.solve(x4, b4, rtol=1e-10, max_it=100, flexible=True, n_vec=8)
         solves["cube12_spheres_q6_pmg_8rhs_fp32_vcycle"] = {
+            "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
+            "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}
+        del s4
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        s4 = mfmg.Solver(m4, 6, mfmg.SCHEME_HP, level_dtypes=[mfmg.F32], max_rhs=8)
+        setup4 = time.time() - t0
+        x4.zero_()
+        st = s4.solve(x4, b4, rtol=1e-10, max_it=100, flexible=True, n_vec=8)
+        solves["cube12_spheres_q6_hp_8rhs_fp32_vcycle"] = {
             "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
             "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}
         del s4

@@ -93,9 +93,15 @@ typedef struct {
  *  LS_THEN_P local smoothing down to the coarse grid, then polynomial
  *           coarsening on the coarse grid (levels 0 .. P-1 have degrees
  *           1, 2, ..., floor(k/2); they cover the domain, have no edge and
- *           receive no copied right-hand side). */
+ *           receive no copied right-hand side).
+ *  HP       geometric and polynomial global coarsening in one step (the
+ *           option the paper's outlook names): each level coarsens the
+ *           mesh once and halves the degree, while both are possible;
+ *           then the remaining one alone.  The transfer of such a step
+ *           interpolates the coarse degree-k/2 function of a parent cell
+ *           at the degree-k nodes of its children. */
 enum { MFMG_SCHEME_H = 0, MFMG_SCHEME_P_THEN_H = 1, MFMG_SCHEME_H_THEN_P = 2, MFMG_SCHEME_LS = 3,
-       MFMG_SCHEME_LS_THEN_P = 4 };
+       MFMG_SCHEME_LS_THEN_P = 4, MFMG_SCHEME_HP = 5 };
 
 /* Level index of the active mesh (the leaves) in every call that takes a
  * level: the finest level under global coarsening, the operator of the leaves
@@ -120,6 +126,12 @@ typedef struct {
   double eig_safety;     /* lambda_max = safety * estimate, 0 -> 1.2 */
   int eig_iterations;    /* CG-Lanczos steps for the estimate, 0 -> 15 */
   int max_rhs;           /* largest n_vec of vcycle/solve, 0 -> 1 (max 8) */
+  int drop_coarse;       /* global-coarsening schemes: leave out this many of
+                            the coarsest levels, so that the exact coarse
+                            solver acts on a finer level, possibly one with
+                            hanging nodes (the early switch of the paper's
+                            outlook); 0 = none.  The new coarsest level must
+                            have at most 12000 DoFs. */
 } mfmg_level_desc;
 
 typedef struct {

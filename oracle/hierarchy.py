@@ -11,6 +11,9 @@ Level sequences, coarse to fine, as (mesh, degree) pairs:
 * ``"h_then_p"`` geometric global coarsening at the finest degree down to the
   coarse grid, then bisection of the degree on the coarse grid (used to make
   the coarse problem small enough for a direct solve).
+* ``"hp"``     geometric and polynomial coarsening in the same step while both
+  are possible, then the remaining one alone (the variant that the outlook,
+  Section 8, leaves to future work).
 """
 from __future__ import annotations
 
@@ -36,14 +39,23 @@ def level_pairs(tree, k, scheme="h"):
     elif scheme == "h_then_p":
         degs = degree_sequence(k)
         pairs = [(m, k) for m in meshes] + [(meshes[-1], d) for d in degs[1:]]
+    elif scheme == "hp":
+        # mesh and degree coarsened in the same step while both can be
+        degs = degree_sequence(k)
+        pairs = [(meshes[min(i, len(meshes) - 1)], degs[min(i, len(degs) - 1)])
+                 for i in range(max(len(meshes), len(degs)))]
     else:
         raise ValueError(scheme)
     return pairs[::-1]
 
 
 class Hierarchy:
-    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True):
-        self.pairs = level_pairs(tree, k, scheme)
+    """``drop_coarse`` leaves out that many of the coarsest levels: the direct
+    coarse solve then acts on a finer level, which may have hanging nodes
+    (the early switch to the coarse-grid solver of the outlook, Section 8)."""
+
+    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0):
+        self.pairs = level_pairs(tree, k, scheme)[drop_coarse:]
         self.spaces = [Space(m, d, dirichlet=dirichlet) for m, d in self.pairs]
         self.levels = []
         for l, S in enumerate(self.spaces):

@@ -160,4 +160,18 @@ inline std::vector<double> p_transfer_matrix(int kf, int kc) {
   return T;
 }
 
+// h and p coarsening in one step: the coarse degree-kc basis on [0,1]
+// evaluated at the degree-kf nodes of the two halves (2 kf + 1 points, the
+// shared middle node once), row-major (2 kf + 1) x (kc + 1)
+inline std::vector<double> hp_transfer_matrix(int kf, int kc) {
+  std::vector<double> nf = gll_nodes(kf), nc = gll_nodes(kc);
+  const int m = 2 * kf + 1;
+  std::vector<double> T(m * (kc + 1));
+  for (int I = 0; I < m; ++I) {
+    const double t = (I <= kf) ? 0.5 * nf[I] : 0.5 * (1.0 + nf[I - kf]);
+    for (int j = 0; j <= kc; ++j) T[I * (kc + 1) + j] = Tables1D::clean(lagrange(nc, j, t));
+  }
+  return T;
+}
+
 }  // namespace mfmg

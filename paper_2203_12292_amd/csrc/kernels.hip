@@ -1413,6 +1413,9 @@ TrTab<T, NF, NC> make_trtab(int kf, int kc) {
   }
   if (kf == kc && NF == 2 * kc + 1) {
     for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>(tc.T[i]);
+  } else if (kf != kc && NF == 2 * kf + 1) {
+    std::vector<double> P = hp_transfer_matrix(kf, kc);
+    for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>(P[i]);
   } else if (kf != kc) {
     std::vector<double> P = p_transfer_matrix(kf, kc);
     for (int i = 0; i < NF * NC; ++i) t.P[i] = static_cast<T>(P[i]);
@@ -1449,11 +1452,31 @@ void transfer_h(bool prolong, const CellView& f, const CellView& c, const Transf
                                      dst, src, s);
 }
 
+// geometric and polynomial coarsening in one step: identity pairs change the
+// degree only, refined groups change both
+template <int KF, int KC, typename S>
+void transfer_hp(bool prolong, const CellView& f, const CellView& c, const TransferView& t, int nv, void* dst,
+                 const void* src, hipStream_t s) {
+  transfer_launch<KF, KC, KF + 1, S>(prolong, f, c, t, t.ident_coarse, t.ident_fine, t.n_ident, 1, nv, dst, src, s);
+  transfer_launch<KF, KC, 2 * KF + 1, S>(prolong, f, c, t, t.refined_coarse, t.refined_fine, t.n_refined, 8, nv,
+                                         dst, src, s);
+}
+
 template <typename S>
 void transfer_s(bool prolong, const CellView& f, const CellView& c, const TransferView& t, int nv, void* dst,
                 const void* src, hipStream_t s) {
+  if (!t.polynomial && f.k != c.k) {
+    switch (f.k * 10 + c.k) {
+      case 21: transfer_hp<2, 1, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 31: transfer_hp<3, 1, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 42: transfer_hp<4, 2, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 52: transfer_hp<5, 2, S>(prolong, f, c, t, nv, dst, src, s); break;
+      case 63: transfer_hp<6, 3, S>(prolong, f, c, t, nv, dst, src, s); break;
+      default: throw Error(MFMG_ERR_UNSUPPORTED, "combined h and p transfer pair");
+    }
+    return;
+  }
   if (!t.polynomial) {
-    MFMG_REQUIRE(f.k == c.k, MFMG_ERR_INVALID_ARG, "geometric transfer needs equal degrees");
     switch (f.k) {
       case 1: transfer_h<1, S>(prolong, f, c, t, nv, dst, src, s); break;
       case 2: transfer_h<2, S>(prolong, f, c, t, nv, dst, src, s); break;

@@ -120,6 +120,16 @@ std::vector<std::pair<int, int>> level_pairs(int n_meshes, int k, int scheme) {
   } else if (scheme == MFMG_SCHEME_H_THEN_P) {
     for (int m = fine; m >= 0; --m) p.push_back({m, k});
     for (size_t i = 1; i < degs.size(); ++i) p.push_back({0, degs[i]});
+  } else if (scheme == MFMG_SCHEME_HP) {
+    // mesh and degree coarsened together while both can be; then whichever is left
+    size_t d = 0;
+    int m = fine;
+    p.push_back({m, degs[0]});
+    while (m > 0 || d + 1 < degs.size()) {
+      if (m > 0) --m;
+      if (d + 1 < degs.size()) ++d;
+      p.push_back({m, degs[d]});
+    }
   } else {
     throw Error(MFMG_ERR_INVALID_ARG, "unknown level scheme");
   }
@@ -288,6 +298,8 @@ int level_dtype(const mfmg_level_desc& desc, int l) {
 // ones only) with the same entities of the active mesh.
 void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vector<LevelDofs>& host, hipStream_t s) {
   MFMG_REQUIRE(desc.dirichlet != 0, MFMG_ERR_UNSUPPORTED, "local smoothing needs Dirichlet boundary conditions");
+  MFMG_REQUIRE(desc.drop_coarse == 0, MFMG_ERR_UNSUPPORTED,
+               "local smoothing switches to the coarse solver only on a level that covers the domain");
   const Octree& tree = ctx.meshes.back();
   std::vector<int> lv;
   for (int l = 0; l <= tree.n_levels(); ++l)
@@ -373,7 +385,10 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   if (desc.scheme == MFMG_SCHEME_LS || desc.scheme == MFMG_SCHEME_LS_THEN_P) {
     setup_local_smoothing(ctx, desc, host, s);
   } else {
-    const auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);
+    auto pairs = level_pairs(static_cast<int>(ctx.meshes.size()), desc.degree, desc.scheme);
+    MFMG_REQUIRE(desc.drop_coarse >= 0 && desc.drop_coarse < static_cast<int>(pairs.size()), MFMG_ERR_INVALID_ARG,
+                 "drop_coarse must leave at least one level");
+    pairs.erase(pairs.begin(), pairs.begin() + desc.drop_coarse);  // early switch to the coarse solver
     MFMG_REQUIRE(pairs.size() <= MFMG_MAX_LEVELS, MFMG_ERR_UNSUPPORTED, "too many levels");
     const int nl = static_cast<int>(pairs.size());
     ctx.levels.clear();

@@ -20,7 +20,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP_ERROR", -4: "OOM", -5: 
 (ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN,
  ERR_NET_REJECTED) = -1, -2, -3, -4, -5, -6, -7
 F64, F32, BF16 = 0, 1, 2
-SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P, SCHEME_LS, SCHEME_LS_THEN_P = 0, 1, 2, 3, 4
+SCHEME_H, SCHEME_P_THEN_H, SCHEME_H_THEN_P, SCHEME_LS, SCHEME_LS_THEN_P, SCHEME_HP = 0, 1, 2, 3, 4, 5
 LEVEL_ACTIVE = -1  # the leaves (the outer solver's mesh)
 RHS_CONST, RHS_GAUSS, RHS_SINE = 0, 1, 2
 COARSE_EXACT, COARSE_LEARNED, COARSE_ZERO = 0, 1, 2
@@ -43,7 +43,7 @@ class LevelDesc(C.Structure):
     _fields_ = [("degree", C.c_int), ("scheme", C.c_int), ("dirichlet", C.c_int),
                 ("n_level_dtype", C.c_int), ("level_dtype", C.c_int * MAX_LEVELS),
                 ("cheb_degree", C.c_int), ("smoothing_range", C.c_double), ("eig_safety", C.c_double),
-                ("eig_iterations", C.c_int), ("max_rhs", C.c_int)]
+                ("eig_iterations", C.c_int), ("max_rhs", C.c_int), ("drop_coarse", C.c_int)]
 
 
 class NetTrainDesc(C.Structure):
@@ -212,7 +212,7 @@ class Solver:
     """Multigrid levels on the GPU (``mfmg_setup_levels``) and the hot-path calls."""
 
     def __init__(self, mesh, degree, scheme=SCHEME_H, level_dtypes=None, dirichlet=True, cheb_degree=3,
-                 max_rhs=1, smoothing_range=20.0, eig_safety=1.2, eig_iterations=15):
+                 max_rhs=1, smoothing_range=20.0, eig_safety=1.2, eig_iterations=15, drop_coarse=0):
         d = LevelDesc()
         d.degree, d.scheme, d.dirichlet = degree, scheme, int(dirichlet)
         level_dtypes = list(level_dtypes or [])
@@ -220,7 +220,7 @@ class Solver:
         for i, t in enumerate(level_dtypes):
             d.level_dtype[i] = t
         d.cheb_degree, d.smoothing_range, d.eig_safety = cheb_degree, smoothing_range, eig_safety
-        d.eig_iterations, d.max_rhs = eig_iterations, max_rhs
+        d.eig_iterations, d.max_rhs, d.drop_coarse = eig_iterations, max_rhs, drop_coarse
         self.desc = d
         self.handle = C.c_void_p()
         self.mesh = mesh

@@ -35,4 +35,4 @@ DESCS = {
                                      [(synth.SPHERE_CUT, (0.0, 0.0, 0.0, 0.3, 0.7))] * 2),
 }
 
-SCHEME_CODES = {"h": 0, "p_then_h": 1, "h_then_p": 2}
+SCHEME_CODES = {"h": 0, "p_then_h": 1, "h_then_p": 2, "hp": 5}

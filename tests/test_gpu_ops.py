@@ -102,7 +102,9 @@ def test_rhs(name, k):
 
 @pytest.mark.parametrize("name,k,scheme", [("tiny", 1, "h"), ("tiny", 2, "h"), ("small", 3, "h"),
                                            ("small", 4, "h"), ("small", 6, "p_then_h"),
-                                           ("small", 5, "p_then_h"), ("tiny", 4, "h_then_p")])
+                                           ("small", 5, "p_then_h"), ("tiny", 4, "h_then_p"),
+                                           ("tiny", 2, "hp"), ("small", 4, "hp"), ("small", 6, "hp"),
+                                           ("small_m1", 5, "hp")])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_transfer(name, k, scheme, dtype):
     H = oracle_hierarchy(name, k, scheme)
@@ -176,7 +178,7 @@ def test_coarse_solve(name, k):
 
 
 @pytest.mark.parametrize("name,k,scheme", [("tiny", 2, "h"), ("small", 4, "h"), ("tiny", 4, "p_then_h"),
-                                           ("tiny", 2, "h_then_p")])
+                                           ("tiny", 2, "h_then_p"), ("small", 4, "hp"), ("small", 6, "hp")])
 def test_vcycle(name, k, scheme):
     H = oracle_hierarchy(name, k, scheme)
     S = gpu_solver(name, k, scheme)
@@ -190,7 +192,8 @@ def test_vcycle(name, k, scheme):
     assert rel_err(from_gpu(xg, P[-1]), H.vcycle(b)) < 1e-11
 
 
-@pytest.mark.parametrize("name,k,scheme", [("tiny", 2, "h"), ("cfg1", 2, "h"), ("small", 4, "p_then_h")])
+@pytest.mark.parametrize("name,k,scheme", [("tiny", 2, "h"), ("cfg1", 2, "h"), ("small", 4, "p_then_h"),
+                                           ("small", 4, "hp")])
 def test_solve_fp64(name, k, scheme):
     from paper_2203_12292_amd import mfmg
     H = oracle_hierarchy(name, k, scheme)
@@ -281,3 +284,33 @@ def test_discretisation_convergence_on_gpu(k):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     print(f"[conv k={k}] errors {errs} rates {rates}")
     assert rates[-1] > k + 1 - 0.3
+
+
+@pytest.mark.parametrize("drop", [1, 2])
+def test_early_coarse_switch(drop):
+    """Coarse solve on a finer level with hanging nodes (the coarsest `drop`
+    levels left out): V-cycle parity with the oracle and the FP64 solve."""
+    from oracle.hierarchy import Hierarchy
+    from paper_2203_12292_amd import mfmg
+    from helpers import oracle_tree
+    H = Hierarchy(oracle_tree("cfg1"), 2, "h", drop_coarse=drop)
+    print(f"[setup] cfg1 k=2 drop_coarse={drop}", flush=True)
+    S = mfmg.Solver(mfmg.Mesh(DESCS["cfg1"]), 2, mfmg.SCHEME_H, drop_coarse=drop)
+    assert S.n_levels == len(H.levels) and S.level_info(0)["n_hanging_cells"] > 0
+    P = [perm_from_codes(H.spaces[l].codes_array(), S.dof_codes(l)) for l in range(S.n_levels)]
+    for l in range(1, S.n_levels):
+        H.levels[l].lmin, H.levels[l].lmax = S.smoother_range(l)
+    b = np.random.default_rng(2).uniform(-1, 1, H.fine.A.shape[0])
+    xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+    S.vcycle(xg, to_gpu(b, P[-1]))
+    bg = torch.zeros_like(xg)
+    S.rhs(bg)
+    xs = torch.zeros_like(xg)
+    st = S.solve(xs, bg, rtol=1e-12, max_it=60)
+    torch.cuda.synchronize()
+    assert rel_err(from_gpu(xg, P[-1]), H.vcycle(b)) < 1e-11
+    xo = solvers.direct_solve(H.fine.A, assemble_load(H.spaces[-1], constant(1.0)))
+    err = np.linalg.norm(from_gpu(xs, P[-1]) - xo) / np.linalg.norm(xo)
+    print(f"[solve] drop_coarse={drop}: {st['iterations']} it, err {err:.2e}", flush=True)
+    assert st["converged"] and err < 1e-10
+    S.close()

@@ -89,3 +89,37 @@ def test_flexible_cg_same_as_standard_for_fixed_preconditioner(hier):
     x2, it2, _ = hier.solve(b, 1e-10, flexible=True)
     assert it1 == it2
     assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+
+
+@pytest.mark.parametrize("drop", [1, 2])
+def test_early_coarse_switch(drop):
+    """The direct coarse solve on a finer level (with hanging nodes) still gives
+    a symmetric positive definite V-cycle, and PCG reaches the direct solution
+    in no more iterations than with the full hierarchy."""
+    from helpers import oracle_tree
+    tree = oracle_tree("cfg1")
+    H = Hierarchy(tree, 2, "h", drop_coarse=drop)
+    full = Hierarchy(tree, 2, "h")
+    assert len(H.levels) == len(full.levels) - drop
+    assert any(H.spaces[0].cell_has_hanging(c) for c in H.spaces[0].cells)
+    rng = np.random.default_rng(21)
+    u, v = rng.standard_normal(H.fine.A.shape[0]), rng.standard_normal(H.fine.A.shape[0])
+    Bu, Bv = H.vcycle(u), H.vcycle(v)
+    assert abs(u @ Bv - v @ Bu) <= 1e-12 * abs(u @ Bv) and u @ Bu > 0
+    b = assemble_load(H.spaces[-1], constant(1.0))
+    x, it, _ = H.solve(b, rtol=1e-10)
+    _, it_full, _ = full.solve(b, rtol=1e-10)
+    xd = solvers.direct_solve(H.fine.A, b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd) and it <= it_full
+
+
+def test_switch_on_finest_level_is_exact():
+    """Leaving out every level but the finest makes the V-cycle the exact
+    inverse: PCG converges in one iteration."""
+    from helpers import oracle_tree
+    tree = oracle_tree("tiny")
+    n = len(Hierarchy(tree, 2, "h").levels)
+    H = Hierarchy(tree, 2, "h", drop_coarse=n - 1)
+    b = assemble_load(H.spaces[-1], constant(1.0))
+    _, it, _ = H.solve(b, rtol=1e-12)
+    assert len(H.levels) == 1 and it == 1

@@ -110,11 +110,13 @@ def test_uniform_q1_stencil():
         assert abs(A[centre, j] - want) < 1e-15
 
 
-@pytest.mark.parametrize("k,scheme", [(1, "h"), (2, "h"), (3, "h"), (4, "p")])
+@pytest.mark.parametrize("k,scheme", [(1, "h"), (2, "h"), (3, "h"), (4, "p"), (2, "hp"), (4, "hp"), (6, "hp")])
 def test_galerkin_identity(tiny, k, scheme):
     if scheme == "h":
         coarse_tree = tiny.coarsened()
         Sf, Sc = Space(tiny, k), Space(coarse_tree, k)
+    elif scheme == "hp":  # mesh coarsened and degree halved in one step
+        Sf, Sc = Space(tiny, k), Space(tiny.coarsened(), k // 2)
     else:
         Sf, Sc = Space(tiny, k), Space(tiny, k // 2)
     P = prolongation(Sf, Sc)
@@ -123,7 +125,8 @@ def test_galerkin_identity(tiny, k, scheme):
     assert np.abs(G).max() < 1e-13 * abs(Ac).max()
 
 
-@pytest.mark.parametrize("kf,kc,h", [(2, 2, True), (4, 2, False), (3, 1, False), (6, 3, False)])
+@pytest.mark.parametrize("kf,kc,h", [(2, 2, True), (4, 2, False), (3, 1, False), (6, 3, False), (4, 2, True),
+                                     (6, 3, True), (2, 1, True)])
 def test_prolongation_reproduces_polynomials(small, kf, kc, h):
     coarse_tree = small.coarsened() if h else small
     Sf, Sc = Space(small, kf, dirichlet=False), Space(coarse_tree, kc, dirichlet=False)
