@@ -73,5 +73,8 @@ class Hierarchy:
     def vcycle(self, b):
         return solvers.vcycle(self.levels, b, self.coarse)
 
+    def fmg(self, b, cycles=1):
+        return solvers.fmg(self.levels, b, self.coarse, cycles)
+
     def solve(self, b, rtol=1e-10, max_it=200, flexible=False):
         return solvers.pcg(self.fine.A, b, self.vcycle, rtol, max_it, flexible)

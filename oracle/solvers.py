@@ -14,6 +14,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * V-cycle (Algorithms 1-2, global-coarsening branch, A^(l) = A_SS^(l)).
 * CG preconditioned by one V-cycle per iteration (Section 2), x0 = 0, stopped
   on the l2 norm of the unpreconditioned residual relative to ||b||.
+* Full multigrid (textbook; named by the paper as a benefit of global
+  coarsening).
 """
 from __future__ import annotations
 
@@ -128,6 +130,28 @@ def vcycle(levels, b, coarse_solver, l=None):
     xc = vcycle(levels, bc, coarse_solver, l - 1)                       # recursion
     x = x + L.P @ xc                                                    # prolongate-add
     x = chebyshev(L.A, L.Dinv, b, x, L.degree, L.lmin, L.lmax)          # postsmoothing
+    return x
+
+
+def fmg(levels, b, coarse_solver, cycles=1):
+    """Full multigrid with V-cycles (textbook form: Trottenberg, Oosterlee,
+    Schueller, Multigrid, 2001, Sec. 2.6), which the paper names as a solver
+    that global coarsening makes easy to build (Section 2.2).
+
+    The right-hand side is carried to every level by the restriction,
+    b^(l-1) = P^T b^(l); the coarsest level is solved exactly; then on each
+    finer level the prolongated coarse result is the initial guess and
+    ``cycles`` V-cycles correct it, x <- x + V(b - A x).
+    """
+    bs = [None] * len(levels)
+    bs[-1] = b
+    for l in range(len(levels) - 1, 0, -1):
+        bs[l - 1] = levels[l].P.T @ bs[l]
+    x = coarse_solver(bs[0])
+    for l in range(1, len(levels)):
+        x = levels[l].P @ x
+        for _ in range(cycles):
+            x = x + vcycle(levels, bs[l] - levels[l].A @ x, coarse_solver, l)
     return x
 
 

@@ -123,3 +123,45 @@ def test_switch_on_finest_level_is_exact():
     b = assemble_load(H.spaces[-1], constant(1.0))
     _, it, _ = H.solve(b, rtol=1e-12)
     assert len(H.levels) == 1 and it == 1
+
+
+def _sine_problem(g, k):
+    from oracle.space import l2_error
+    desc = synth.mesh_desc(f"cube2_g{g}_ball", 2, 0.0, 1.0, g, [(synth.BALL, (0.0, 0.0, 0.0, 0.45))])
+    H = Hierarchy(octree.build_mesh(desc), k, "h")
+
+    def u(p):
+        return np.sin(np.pi * p[:, 0]) * np.sin(np.pi * p[:, 1]) * np.sin(np.pi * p[:, 2])
+    b = assemble_load(H.spaces[-1], lambda p: 3 * np.pi ** 2 * u(p))
+    return H, b, u, l2_error
+
+
+@pytest.mark.parametrize("k,gs", [(1, (1, 2, 3)), (2, (1, 2))])
+def test_fmg_reaches_discretisation_accuracy(k, gs):
+    """FMG with two V-cycles per level solves to the size of the
+    discretisation error at every mesh size (the defining property of full
+    multigrid): its algebraic error in the energy norm stays below a quarter
+    of the discretisation error ||u - u_h||_A (from Galerkin orthogonality,
+    ||u - u_h||_A^2 = ||u||_A^2 - u_h^T A u_h with ||u||_A^2 = 3 pi^2 / 8 for
+    u = sin(pi x) sin(pi y) sin(pi z)), and its L2 error stays within 1.2x
+    of u_h's and converges at the rate h^(k+1)."""
+    e_fmg = []
+    for g in gs:
+        H, b, u, l2_error = _sine_problem(g, k)
+        S = H.spaces[-1]
+        xh = solvers.direct_solve(H.fine.A, b)
+        x = H.fmg(b, cycles=2)
+        e_disc = np.sqrt(3 * np.pi ** 2 / 8 - xh @ (H.fine.A @ xh))
+        e_alg = np.sqrt((x - xh) @ (H.fine.A @ (x - xh)))
+        assert e_alg <= 0.25 * e_disc, (g, e_alg, e_disc)
+        e_fmg.append(l2_error(S, x, u))
+        assert e_fmg[-1] <= 1.2 * l2_error(S, xh, u), g
+    rates = np.log2(np.array(e_fmg[:-1]) / np.array(e_fmg[1:]))
+    assert rates[-1] > k + 1 - 0.5, rates
+
+
+def test_fmg_with_many_cycles_is_the_discrete_solution():
+    H, b, _, _ = _sine_problem(1, 2)
+    x = H.fmg(b, cycles=30)
+    xd = solvers.direct_solve(H.fine.A, b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
