@@ -373,6 +373,23 @@ def main():
         st = solver.solve(xs, b, rtol=1e-10, max_it=100)
         solves["cube16_q4_fp64"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                                     "residual": st["final_residual"]}
+        # full multigrid: one pass, one or two V-cycles per level; its distance to
+        # the converged PCG solution (1e-10) is the algebraic error it leaves
+        r = torch.empty_like(b)
+        x_ref = xs.clone()
+        for cycles in (1, 2):
+            for _ in range(2):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solver.fmg(xs, b, cycles=cycles)
+                e1.record()
+                torch.cuda.synchronize()
+            solver.vmult(fine, r, xs)
+            res = float(torch.linalg.norm(b - r) / torch.linalg.norm(b))
+            err = float(torch.linalg.norm(xs - x_ref) / torch.linalg.norm(x_ref))
+            solves[f"cube16_q4_fmg_{cycles}_vcycles"] = {"seconds": e0.elapsed_time(e1) * 1e-3,
+                                                       "relative_residual": res,
+                                                       "relative_distance_to_solution": err}
         del solver
         torch.cuda.empty_cache()
         s32 = mfmg.Solver(mesh, k, mfmg.SCHEME_H_THEN_P, level_dtypes=[mfmg.F32])

@@ -250,6 +250,17 @@ int mfmg_coarse_solve(mfmg_ctx ctx, int dtype, int n_vec, void* x, const void* b
  * n_vec <= max_rhs. */
 int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* stream);
 
+/* [async] Full multigrid (textbook FMG with V-cycles; the paper names it as a
+ * solver that global coarsening makes easy to build, Section 2.2): b (FP64,
+ * finest level) is restricted to every level, b^(l-1) = P^T b^(l); the
+ * coarsest level is solved exactly; on each finer level the prolongated
+ * coarser result is the initial guess of `cycles` V-cycles (Algorithm 2,
+ * presmoothing from that guess).  x (FP64) receives the finest result.
+ * Global-coarsening schemes only (MFMG_ERR_UNSUPPORTED under local
+ * smoothing); 1 <= cycles <= 16; n_vec <= max_rhs.  Uses the levels' work
+ * vectors, like mfmg_vcycle. */
+int mfmg_fmg(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, int cycles, void* stream);
+
 /* [async] Algorithm 1, copy to the levels, for level l: dst (level storage
  * type, [n_dofs(l)][n_vec]) is zeroed, then receives the values of the
  * active-mesh vector src (FP64) at the active DoFs that belong to level l.

@@ -353,6 +353,19 @@ int mfmg_vcycle(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, void* s
   });
 }
 
+int mfmg_fmg(mfmg_ctx ctx, int n_vec, void* x_f64, const void* b_f64, int cycles, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    require_dirichlet(ctx->ctx);
+    check_vec(x_f64, ctx->ctx.fine().n_dofs, "x");
+    check_vec(b_f64, ctx->ctx.fine().n_dofs, "b");
+    if (ctx->ctx.fine().n_dofs == 0) return MFMG_OK;
+    mfmg::fmg(ctx->ctx, n_vec, static_cast<double*>(x_f64), static_cast<const double*>(b_f64), cycles,
+              as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
 int mfmg_copy_to_mg(mfmg_ctx ctx, int level, int n_vec, void* dst, const void* src_f64, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");

@@ -105,6 +105,7 @@ void level_prolongate_add(Context& ctx, int fine, int dtype, int nv, void* dst, 
 void level_restrict_add(Context& ctx, int fine, int dtype, int nv, void* dst, const void* src, hipStream_t s);
 void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipStream_t s);
 void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s);
+void fmg(Context& ctx, int nv, double* x, const double* b, int cycles, hipStream_t s);
 void copy_to_mg(Context& ctx, int l, int nv, void* dst, const double* src, hipStream_t s);
 void copy_from_mg(Context& ctx, int l, int nv, double* dst, const void* src, hipStream_t s);
 int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,

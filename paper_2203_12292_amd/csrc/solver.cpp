@@ -533,38 +533,67 @@ void coarse_solve(Context& ctx, int dtype, int nv, void* x, const void* b, hipSt
 namespace {
 void coarse_level_solve(Context& ctx, int nv, hipStream_t s);
 
-void vcycle_level(Context& ctx, int l, int nv, hipStream_t s) {
+// C.b = P^T src (src on level l, in its storage type), through a cast when
+// the two levels store different types
+void restrict_into_zeroed(Context& ctx, int l, int nv, const void* src, hipStream_t s) {
   Level& L = ctx.levels[l];
-  if (l == 0) {
-    coarse_level_solve(ctx, nv, s);
-    return;
-  }
   Level& C = ctx.levels[l - 1];
-  // presmoothing from x = 0
-  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, true, L.lmin, L.lmax, s);
-  // residual
-  level_residual(ctx, l, nv, L.r.ptr, L.b.ptr, L.x.ptr, s);
-  // restriction into a zeroed coarse right-hand side
   launch_fill(0, C.b.ptr, C.n_dofs * nv * static_cast<int64_t>(dtype_size(C.dtype)), s);
   if (C.dtype == L.dtype) {
-    level_restrict_add(ctx, l, L.dtype, nv, C.b.ptr, L.r.ptr, s);
+    level_restrict_add(ctx, l, L.dtype, nv, C.b.ptr, src, s);
   } else {
     launch_fill(0, C.tmp_cast.ptr, C.n_dofs * nv * static_cast<int64_t>(dtype_size(L.dtype)), s);
-    level_restrict_add(ctx, l, L.dtype, nv, C.tmp_cast.ptr, L.r.ptr, s);
+    level_restrict_add(ctx, l, L.dtype, nv, C.tmp_cast.ptr, src, s);
     launch_cast(L.dtype, C.dtype, C.n_dofs * nv, C.tmp_cast.ptr, C.b.ptr, s);
   }
-  vcycle_level(ctx, l - 1, nv, s);
-  // prolongation
+}
+
+// L.x += P C.x
+void prolongate_from_coarse(Context& ctx, int l, int nv, hipStream_t s) {
+  Level& L = ctx.levels[l];
+  Level& C = ctx.levels[l - 1];
   if (C.dtype == L.dtype) {
     level_prolongate_add(ctx, l, L.dtype, nv, L.x.ptr, C.x.ptr, s);
   } else {
     launch_cast(C.dtype, L.dtype, C.n_dofs * nv, C.x.ptr, C.tmp_cast.ptr, s);
     level_prolongate_add(ctx, l, L.dtype, nv, L.x.ptr, C.tmp_cast.ptr, s);
   }
-  // postsmoothing
-  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, false, L.lmin, L.lmax, s);
+}
+
+// Algorithm 2 (global-coarsening branch) on A^(l) x = b^(l); presmoothing
+// starts from x = 0 unless `x_zero` is false (then from the given L.x)
+void vcycle_level(Context& ctx, int l, int nv, hipStream_t s, bool x_zero = true) {
+  Level& L = ctx.levels[l];
+  if (l == 0) {
+    coarse_level_solve(ctx, nv, s);
+    return;
+  }
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, x_zero, L.lmin, L.lmax, s);   // presmoothing
+  level_residual(ctx, l, nv, L.r.ptr, L.b.ptr, L.x.ptr, s);                // residual
+  restrict_into_zeroed(ctx, l, nv, L.r.ptr, s);                           // restriction
+  vcycle_level(ctx, l - 1, nv, s);                                         // coarse correction
+  prolongate_from_coarse(ctx, l, nv, s);                                   // prolongation
+  level_smooth(ctx, l, nv, L.x.ptr, L.b.ptr, false, L.lmin, L.lmax, s);  // postsmoothing
 }
 }  // namespace
+
+void fmg(Context& ctx, int nv, double* x, const double* b, int cycles, hipStream_t s) {
+  MFMG_REQUIRE(!ctx.ls, MFMG_ERR_UNSUPPORTED, "full multigrid runs on global-coarsening levels");
+  MFMG_REQUIRE(nv >= 1 && nv <= ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
+  MFMG_REQUIRE(cycles >= 1 && cycles <= 16, MFMG_ERR_INVALID_ARG, "cycles must be in [1, 16]");
+  const int top = static_cast<int>(ctx.levels.size()) - 1;
+  Level& F = ctx.levels[top];
+  launch_cast(MFMG_F64, F.dtype, F.n_dofs * nv, b, F.b.ptr, s);
+  for (int l = top; l >= 1; --l) restrict_into_zeroed(ctx, l, nv, ctx.levels[l].b.ptr, s);  // b^(l-1) = P^T b^(l)
+  coarse_level_solve(ctx, nv, s);
+  for (int l = 1; l <= top; ++l) {
+    Level& L = ctx.levels[l];
+    launch_fill(0, L.x.ptr, L.n_dofs * nv * static_cast<int64_t>(dtype_size(L.dtype)), s);
+    prolongate_from_coarse(ctx, l, nv, s);  // initial guess from the coarser level
+    for (int c = 0; c < cycles; ++c) vcycle_level(ctx, l, nv, s, false);
+  }
+  launch_cast(F.dtype, MFMG_F64, F.n_dofs * nv, F.x.ptr, x, s);
+}
 
 namespace {
 void coarse_level_solve(Context& ctx, int nv, hipStream_t s) {

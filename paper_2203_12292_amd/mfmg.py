@@ -81,6 +81,7 @@ _SIGS = {
     "mfmg_restrict_add": (_I, [_P, _I, _I, _I, _P, _P, _P]),
     "mfmg_coarse_solve": (_I, [_P, _I, _I, _P, _P, _P]),
     "mfmg_vcycle": (_I, [_P, _I, _P, _P, _P]),
+    "mfmg_fmg": (_I, [_P, _I, _P, _P, _I, _P]),
     "mfmg_copy_to_mg": (_I, [_P, _I, _I, _P, _P, _P]),
     "mfmg_copy_from_mg": (_I, [_P, _I, _I, _P, _P, _P]),
     "mfmg_level_edge": (_I, [_P, _I, _I64P, C.POINTER(C.c_uint8)]),
@@ -291,6 +292,10 @@ class Solver:
 
     def coarse_solve(self, x, b, n_vec=1):
         _check(lib().mfmg_coarse_solve(self.handle, _dtype_code(x), n_vec, _ptr(x), _ptr(b), _stream()))
+        return x
+
+    def fmg(self, x, b, cycles=1, n_vec=1):
+        _check(lib().mfmg_fmg(self.handle, n_vec, _ptr(x), _ptr(b), cycles, _stream()))
         return x
 
     def copy_to_mg(self, level, dst, src, n_vec=1):

@@ -236,3 +236,12 @@ def test_vcycle_with_polynomial_coarse_levels(name, k):
     err = np.linalg.norm(from_gpu(xs, PA) - xo) / np.linalg.norm(xo)
     print(f"[ls+p solve] {name} k={k}: {st['iterations']} it, err {err:.2e}", flush=True)
     assert st["converged"] and err < 1e-10
+
+
+def test_fmg_is_not_offered_under_local_smoothing():
+    from paper_2203_12292_amd import mfmg
+    S = gpu_ls("tiny", 2)
+    x = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
+    with pytest.raises(mfmg.MfmgError) as e:
+        S.fmg(x, x.clone())
+    assert e.value.code == mfmg.ERR_UNSUPPORTED

@@ -314,3 +314,19 @@ def test_early_coarse_switch(drop):
     print(f"[solve] drop_coarse={drop}: {st['iterations']} it, err {err:.2e}", flush=True)
     assert st["converged"] and err < 1e-10
     S.close()
+
+
+@pytest.mark.parametrize("name,k,scheme,cycles", [("tiny", 2, "h", 1), ("small", 4, "h_then_p", 2),
+                                                  ("cfg1", 2, "h", 2), ("small", 6, "p_then_h", 1)])
+def test_fmg(name, k, scheme, cycles):
+    """Full multigrid against the oracle's (same smoother intervals)."""
+    H = oracle_hierarchy(name, k, scheme)
+    S = gpu_solver(name, k, scheme)
+    P = perms(name, k, scheme)
+    for l in range(1, S.n_levels):
+        H.levels[l].lmin, H.levels[l].lmax = S.smoother_range(l)
+    b = np.random.default_rng(8).uniform(-1, 1, H.fine.A.shape[0])
+    xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+    S.fmg(xg, to_gpu(b, P[-1]), cycles=cycles)
+    torch.cuda.synchronize()
+    assert rel_err(from_gpu(xg, P[-1]), H.fmg(b, cycles)) < 1e-11
