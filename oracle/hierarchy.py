@@ -54,9 +54,9 @@ class Hierarchy:
     coarse solve then acts on a finer level, which may have hanging nodes
     (the early switch to the coarse-grid solver of the outlook, Section 8)."""
 
-    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0):
+    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0, coef=None):
         self.pairs = level_pairs(tree, k, scheme)[drop_coarse:]
-        self.spaces = [Space(m, d, dirichlet=dirichlet) for m, d in self.pairs]
+        self.spaces = [Space(m, d, dirichlet=dirichlet, coef=coef) for m, d in self.pairs]
         self.levels = []
         for l, S in enumerate(self.spaces):
             A = assemble_stiffness(S)

@@ -37,7 +37,7 @@ import numpy as np
 from . import fe, octree, solvers
 from .hierarchy import degree_sequence
 from .octree import _unpack3, pack
-from .space import Space, assemble_stiffness, prolongation
+from .space import Space, assemble_stiffness, coefficient, prolongation
 
 
 class _LevelIndex:
@@ -56,8 +56,9 @@ class LevelSpace(Space):
     """Q_k on all cells of refinement level ``level`` of ``tree``; Dirichlet
     nodes on the domain boundary only; ``edge[i]`` flags refinement-edge DoFs."""
 
-    def __init__(self, tree, level, k):
+    def __init__(self, tree, level, k, coef=None):
         self.tree = tree
+        self.coef = coefficient(coef) if coef is not None else None
         self.level = int(level)
         self.k = int(k)
         self.n = self.k + 1
@@ -165,13 +166,13 @@ class LSHierarchy:
     have no refinement edge and no share of the copied right-hand side.
     """
 
-    def __init__(self, tree, k, cheb_degree=3, coarse_p=False):
-        self.active = Space(tree, k)
+    def __init__(self, tree, k, cheb_degree=3, coarse_p=False, coef=None):
+        self.active = Space(tree, k, coef=coef)
         self.A = assemble_stiffness(self.active)
-        self.spaces = [LevelSpace(tree, l, k) for l in level_numbers(tree)]
+        self.spaces = [LevelSpace(tree, l, k, coef) for l in level_numbers(tree)]
         if coarse_p:
             grid = octree.gc_sequence(tree)[-1]
-            self.spaces = [Space(grid, d) for d in degree_sequence(k)[:0:-1]] + self.spaces
+            self.spaces = [Space(grid, d, coef=coef) for d in degree_sequence(k)[:0:-1]] + self.spaces
         self.levels = []
         for l, V in enumerate(self.spaces):
             P = prolongation(V, self.spaces[l - 1]) if l > 0 else None

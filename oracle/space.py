@@ -39,6 +39,27 @@ from .octree import LeafIndex
 MAXLEV = 20  # finest lattice level of the codes (same constant as synth)
 
 
+def bf16_round(v):
+    """v rounded to the nearest bfloat16 (8 significant bits, ties to even)."""
+    m, e = np.frexp(float(v))                 # v = m 2^e, 1/2 <= m < 1
+    return float(np.ldexp(np.round(np.ldexp(m, 8)), e - 8))   # np.round: ties to even
+
+
+def coefficient(desc):
+    """c(x) of -div(c grad u) from a coefficient descriptor: kind 0 the
+    constant p0 (0 -> 1); kind 1 p4 inside the ball |x - (p0,p1,p2)| <= p3,
+    p5 outside; kind 2 a checkerboard of cubes of edge p2 anchored at
+    (p3,p3,p3), p0 on even and p1 on odd cubes."""
+    kind, p = desc["kind"], list(desc["params"]) + [0.0] * 8
+    if kind == 0:
+        return lambda x: p[0] if p[0] > 0 else 1.0
+    if kind == 1:
+        return lambda x: p[4] if sum((x[d] - p[d]) ** 2 for d in range(3)) <= p[3] ** 2 else p[5]
+    if kind == 2:
+        return lambda x: p[0] if sum(int(np.floor((x[d] - p[3]) / p[2])) for d in range(3)) % 2 == 0 else p[1]
+    raise ValueError(kind)
+
+
 def code1d(l, i, a, k):
     """Exact code of the a-th GLL node of interval i on level l."""
     if a == 0:
@@ -51,10 +72,14 @@ def code1d(l, i, a, k):
 
 
 class Space:
-    """Q_k on the leaves of ``tree``; homogeneous Dirichlet on the boundary."""
+    """Q_k on the leaves of ``tree``; homogeneous Dirichlet on the boundary.
+    ``coef``: a coefficient descriptor (None: c = 1); the operator is then
+    -div(c grad u) with c constant per cell, its value at the cell centre
+    rounded to bfloat16."""
 
-    def __init__(self, tree, k, dirichlet=True, build=True):
+    def __init__(self, tree, k, dirichlet=True, build=True, coef=None):
         self.tree = tree
+        self.coef = coefficient(coef) if coef is not None else None
         self.k = int(k)
         self.n = self.k + 1
         self.dirichlet = dirichlet
@@ -197,6 +222,14 @@ class Space:
     def cell_h(self, cell):
         return self.tree.h(cell[0])
 
+    def cell_coef(self, cell):
+        if self.coef is None:
+            return 1.0
+        l, i, j, m = cell
+        h = self.tree.h(l)
+        centre = self.tree.lo + h * (np.array([i, j, m], float) + 0.5)
+        return bf16_round(self.coef(centre))
+
     def local_constraint_matrix(self, cell):
         """(global ids, dense C_e of shape (n^3, m))."""
         rows = self.cell_rows(cell)
@@ -235,14 +268,14 @@ class Space:
 
 # -- assembled operators -----------------------------------------------------------
 def assemble_stiffness(space):
-    """A = sum_e C_e^T (h_e A_ref) C_e as scipy CSR (n_dofs x n_dofs)."""
+    """A = sum_e C_e^T (c_e h_e A_ref) C_e as scipy CSR (n_dofs x n_dofs)."""
     Aref = fe.reference_stiffness(space.k)
     I, J, V = [], [], []
     for cell in space.cells:
         ids, C = space.local_constraint_matrix(cell)
         if ids.size == 0:
             continue
-        Al = C.T @ (space.cell_h(cell) * Aref) @ C
+        Al = C.T @ ((space.cell_h(cell) * space.cell_coef(cell)) * Aref) @ C
         I.append(np.repeat(ids, ids.size))
         J.append(np.tile(ids, ids.size))
         V.append(Al.ravel())

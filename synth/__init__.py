@@ -50,6 +50,20 @@ KIND_NAMES = {ALL: "all", BALL: "ball", BOX_LE: "box_le", BAND: "band",
 CODE_MAX_LEVEL = 20
 
 
+# Diffusion-coefficient descriptors (kinds as the library's coef_kind): the
+# constant, a ball inclusion, a checkerboard.  Parameters only, no arithmetic.
+COEF_CONST, COEF_BALL, COEF_CHECKER = 0, 1, 2
+
+
+def coef_desc(kind, params):
+    return {"kind": int(kind), "params": [float(p) for p in params]}
+
+
+# a high-contrast inclusion: c = 1000 in the ball of radius 0.3 about
+# (0.5, 0.5, 0.5), 1 elsewhere (the benchmark's coefficient workload)
+COEF_INCLUSION = coef_desc(COEF_BALL, (0.5, 0.5, 0.5, 0.3, 1000.0, 1.0))
+
+
 def mesh_desc(name, n0, lo, hi, n_global, steps):
     return {"name": name, "n0": int(n0), "lo": float(lo), "hi": float(hi),
             "n_global": int(n_global),

@@ -101,7 +101,7 @@ def apply_at(space, cell, xfun):
         for q, row in enumerate(rows):
             for kk, w in row:
                 u[q] += w * cache[kk]
-        return space.cell_h(c) * (Aref @ u)
+        return (space.cell_h(c) * space.cell_coef(c)) * (Aref @ u)
 
     return targets, _accumulate(space, cells, targets, local)
 

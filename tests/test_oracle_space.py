@@ -156,3 +156,34 @@ def test_convergence_rate(k):
         errs.append(l2_error(S, x, u))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > k + 1 - 0.25, (errs, rates)
+
+
+def test_bfloat16_rounding():
+    """Cell coefficients are rounded to bfloat16: 8 significant bits, ties to even."""
+    from oracle.space import bf16_round
+    assert bf16_round(1.0 / 3.0) == 0.333984375          # 0x3EAB
+    assert bf16_round(1000.0) == 1000.0 and bf16_round(0.5) == 0.5
+    assert bf16_round(1.0 + 2.0 ** -8) == 1.0            # halfway, to the even neighbour
+    assert bf16_round(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    assert bf16_round(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_cellwise_coefficient_energy_of_linear_functions(small, k):
+    """-div(c grad u) with c constant per cell, without Dirichlet conditions:
+    constants span the null space, and u = a.x (exact in Q_k, also across
+    hanging faces) has energy |a|^2 sum_e c_e h_e^3 (exact with Gauss
+    quadrature); c = 4 everywhere gives exactly 4 times the Laplacian."""
+    coef = synth.coef_desc(synth.COEF_BALL, (0.2, 0.3, 0.1, 0.45, 1000.0, 1.0 / 3.0))
+    S = Space(small, k, dirichlet=False, coef=coef)
+    A = assemble_stiffness(S)
+    assert np.abs(A @ np.ones(S.n_dofs)).max() < 1e-10 * abs(A).max()
+    a = np.array([0.3, -1.1, 0.7])
+    u = S.dof_points() @ a
+    vol = sum(S.cell_coef(c) * S.cell_h(c) ** 3 for c in S.cells)
+    values = {S.cell_coef(c) for c in S.cells}
+    assert values == {1000.0, 0.333984375}
+    assert abs(u @ (A @ u) - (a @ a) * vol) < 1e-11 * (a @ a) * vol
+    S4 = Space(small, k, coef=synth.coef_desc(synth.COEF_CONST, (4.0,)))
+    S1 = Space(small, k)
+    assert np.abs((assemble_stiffness(S4) - 4.0 * assemble_stiffness(S1)).toarray()).max() == 0.0
