@@ -422,6 +422,21 @@ def main():
                                        "residual": st["final_residual"], "levels": shp.n_levels,
                                        "setup_s": round(setup_hp, 2)}
         del shp
+        # -div(c grad u), c constant per cell: a 1:1000 checkerboard of 0.25-cubes
+        # (aligned with every level's cells), and a c = 1000 ball inclusion
+        # (radius 0.3 about the centre), whose boundary each rediscretised
+        # level resolves differently; the latter is capped at 100 iterations
+        for name, co, cap in (("cube16_q4_checker1000_fp64", synth.COEF_CHECKER_1000, 200),
+                              ("cube16_q4_inclusion1000_fp64", synth.COEF_INCLUSION, 100)):
+            torch.cuda.empty_cache()
+            t0 = time.time()
+            sco = mfmg.Solver(mesh, k, mfmg.SCHEME_H_THEN_P, coef=co)
+            setup_co = time.time() - t0
+            st = sco.solve(xs, b, rtol=1e-10, max_it=cap, raise_on_fail=False)
+            solves[name] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
+                            "converged": st["converged"], "residual": st["final_residual"],
+                            "setup_s": round(setup_co, 2)}
+            del sco
         m1 = mfmg.Mesh(synth.CFG1)
         for drop in (1, 2):  # early switch to the coarse solver, on a level with hanging nodes
             s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, drop_coarse=drop)

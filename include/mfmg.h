@@ -132,6 +132,16 @@ typedef struct {
                             hanging nodes (the early switch of the paper's
                             outlook); 0 = none.  The new coarsest level must
                             have at most 12000 DoFs. */
+  int coef_kind;         /* diffusion coefficient c of -div(c grad u), constant
+                            per cell: c at the cell centre rounded to
+                            bfloat16, on every level's own cells.  0: c =
+                            coef_params[0] (0 -> 1); 1: coef_params[4] inside
+                            the ball |x - p[0..2]| <= p[3], else p[5]; 2:
+                            checkerboard of cubes of edge p[2] anchored at
+                            (p[3],p[3],p[3]), p[0] on even and p[1] on odd
+                            cubes.  c must lie in [1e-30, 1e30].  The load
+                            vector (mfmg_rhs) does not depend on c. */
+  double coef_params[8];
 } mfmg_level_desc;
 
 typedef struct {

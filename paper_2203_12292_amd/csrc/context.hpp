@@ -66,6 +66,7 @@ struct NetState {
 
 struct Context {
   mfmg_level_desc desc{};
+  CoefDesc coef;  // diffusion coefficient (constant per cell)
   std::vector<Octree> meshes;
   std::vector<Level> levels;  // 0 = coarsest
   // local smoothing: `levels` are the refinement levels and `active` is the

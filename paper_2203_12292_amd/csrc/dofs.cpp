@@ -76,7 +76,35 @@ struct EntityRec {
 
 bool LevelDofs::slot_hanging(int64_t c, int s) const { return mfmg::slot_hanging(mask[c], s); }
 
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes, int only_level) {
+double CoefDesc::value(double x, double y, double z) const {
+  switch (kind) {
+    case 0: return p[0] > 0 ? p[0] : 1.0;
+    case 1: {
+      const double dx = x - p[0], dy = y - p[1], dz = z - p[2];
+      return dx * dx + dy * dy + dz * dz <= p[3] * p[3] ? p[4] : p[5];
+    }
+    case 2: {
+      const int64_t s = static_cast<int64_t>(std::floor((x - p[3]) / p[2])) +
+                        static_cast<int64_t>(std::floor((y - p[3]) / p[2])) +
+                        static_cast<int64_t>(std::floor((z - p[3]) / p[2]));
+      return (s % 2 == 0) ? p[0] : p[1];
+    }
+    default: throw Error(MFMG_ERR_INVALID_ARG, "unknown coefficient kind");
+  }
+}
+
+uint32_t coef_mask_bits(double c) {
+  MFMG_REQUIRE(c >= 1e-30 && c <= 1e30, MFMG_ERR_INVALID_ARG, "the coefficient must lie in [1e-30, 1e30]");
+  int e = 0;
+  const double m = std::frexp(c, &e);                       // c = m 2^e, 1/2 <= m < 1
+  const double q = std::nearbyint(std::ldexp(m, 8));        // 8 significant bits, ties to even
+  const float f = static_cast<float>(std::ldexp(q, e - 8));  // exact in float
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
+  return ((b >> 23) & 0xffu) << 24 | ((b >> 16) & 0x7fu) << 9;
+}
+
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes, int only_level,
+                           const CoefDesc* coef) {
   MFMG_REQUIRE(k >= 1 && k <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   LevelDofs L;
   L.k = k;
@@ -143,6 +171,11 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
         if (missing(a1[0], a1[1], a1[2]) || missing(a2[0], a2[1], a2[2]) || missing(a3[0], a3[1], a3[2]))
           m |= 1u << (MASK_EDGE_SHIFT + d);
       }
+    }
+    {
+      const double h = tree.h(x.level);
+      const double xc = tree.lo + (x.i + 0.5) * h, yc = tree.lo + (x.j + 0.5) * h, zc = tree.lo + (x.k + 0.5) * h;
+      m |= coef_mask_bits(coef ? coef->value(xc, yc, zc) : 1.0);
     }
     L.mask[c] = m;
     if (mask_hanging(m)) ++L.n_hanging_cells;
@@ -561,7 +594,7 @@ std::vector<double> assemble_dense(const LevelDofs& L, const Tables1D& t) {
   std::vector<int64_t> dof(n3);
   for (int64_t c = 0; c < L.n_cells; ++c) {
     const uint32_t m = L.mask[c];
-    const double h = L.h0 * std::ldexp(1.0, -mask_level(m));
+    const double h = L.h0 * std::ldexp(1.0, -mask_level(m)) * static_cast<double>(mask_coef(m));
     for (int i = 0; i < n3; ++i)
       for (int j = 0; j < n3; ++j) {
         int a = i % n, b = (i / n) % n, cc = i / (n * n);

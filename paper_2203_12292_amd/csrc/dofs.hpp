@@ -87,13 +87,28 @@ struct LevelDofs {
   bool slot_hanging(int64_t c, int s) const;
 };
 
+// Scalar diffusion coefficient c(x) of the operator -div(c grad u), taken
+// constant per cell: its value at the cell centre rounded to bfloat16 (the
+// form in which the cell mask carries it).  kind 0: c = p[0] (0 -> 1);
+// kind 1: p[4] inside the ball |x - (p[0],p[1],p[2])| <= p[3], else p[5];
+// kind 2: checkerboard of cubes of edge p[2] anchored at (p[3],p[3],p[3]),
+// p[0] on even and p[1] on odd cubes.
+struct CoefDesc {
+  int kind = 0;
+  double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double value(double x, double y, double z) const;
+};
+// mask bits of c rounded to the nearest bfloat16 (ties to even)
+uint32_t coef_mask_bits(double c);
+
 // Builds the DoF numbering and gather maps of `tree` at degree k; `codes`
 // also computes the position codes of all DoFs.  With only_level >= 0 the
 // cells are all cells of that refinement level, refined or not (a
 // local-smoothing level, Section 2.1: a conforming mesh of the region they
 // cover, without hanging nodes); DoFs on the boundary of that region inside
 // the domain are flagged as refinement-edge DoFs.
-LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true, int only_level = -1);
+LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true, int only_level = -1,
+                           const CoefDesc* coef = nullptr);
 
 // Transfer data between a fine level and the next coarser one (Section 3.5).
 // Geometric: every coarse cell is a fine cell (identity category) or the

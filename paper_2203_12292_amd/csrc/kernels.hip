@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
       nx = fetch(cw + BATCH_WAVES * CPW + lc);
       const uint32_t mk = cur.mask;
       const int wave_hang = __any(mask_hanging(mk) ? 1 : 0);
-      const T h = static_cast<T>(ldexp(h0, -mask_level(mk)));
+      const T h = static_cast<T>(ldexp(h0, -mask_level(mk)) * static_cast<double>(mask_coef(mk)));
       T u[N];
       u[0] = in_[cur.g0 + go0];
       u[K] = in_[cur.g1 + go0];
@@ -750,7 +750,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   const int64_t cell = blockIdx.x;
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const uint32_t m = mask[cell];
-  const double h = ldexp(h0, -mask_level(m));
+  const double h = ldexp(h0, -mask_level(m)) * static_cast<double>(mask_coef(m));
   double d[N];  // y-line (x = ta, z = tb)
   if (!mask_hanging(m)) {
 #pragma unroll

@@ -110,6 +110,13 @@ __host__ __device__ inline int mask_face(uint32_t m, int d) { return (m >> (3 + 
 __host__ __device__ inline int mask_edge(uint32_t m, int d) { return (m >> (6 + d)) & 1; }
 __host__ __device__ inline int mask_level(uint32_t m) { return (m >> 16) & 0xff; }
 __host__ __device__ inline bool mask_hanging(uint32_t m) { return (m & 0x1f8u) != 0; }
+// Diffusion coefficient of the cell (constant per cell, positive) as a
+// bfloat16 in the mask bits the layout leaves free: exponent in bits 24-31,
+// the 7 stored mantissa bits in bits 9-15.
+__host__ __device__ inline float mask_coef(uint32_t m) {
+  const uint32_t bits = ((m >> 24) << 23) | (((m >> 9) & 0x7fu) << 16);
+  return __builtin_bit_cast(float, bits);
+}
 
 // Is the line along axis d through local node indices (p, q) of the other two
 // axes (in increasing axis order) interpolated by the hanging-node rule?

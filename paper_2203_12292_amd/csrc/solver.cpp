@@ -325,8 +325,8 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
     L.dtype = level_dtype(desc, l);
     MFMG_REQUIRE(L.dtype == ctx.levels[0].dtype, MFMG_ERR_UNSUPPORTED,
                  "local smoothing needs one storage type on all levels");
-    host[l] = poly_level ? build_level_dofs(ctx.meshes[0], L.k, true, false)
-                         : build_level_dofs(tree, L.k, true, false, L.only_level);
+    host[l] = poly_level ? build_level_dofs(ctx.meshes[0], L.k, true, false, -1, &ctx.coef)
+                         : build_level_dofs(tree, L.k, true, false, L.only_level, &ctx.coef);
     MFMG_REQUIRE(l > np || host[l].n_edge_dofs == 0, MFMG_ERR_INVALID_ARG, "the coarse grid has an edge");
     init_level(ctx, L, host[l], tree.lo, true, s);
     L.n_edge = host[l].n_edge_dofs;
@@ -344,7 +344,7 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
     init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly, !poly), poly);
   }
   // the active mesh (the outer solver's operator), FP64
-  LevelDofs A = build_level_dofs(tree, desc.degree, true, false);
+  LevelDofs A = build_level_dofs(tree, desc.degree, true, false, -1, &ctx.coef);
   Level& F = ctx.active;
   F.mesh = static_cast<int>(ctx.meshes.size()) - 1;
   F.k = desc.degree;
@@ -373,6 +373,9 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
 void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc& desc, hipStream_t s) {
   MFMG_REQUIRE(desc.degree >= 1 && desc.degree <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   ctx.desc = desc;
+  ctx.coef.kind = desc.coef_kind;
+  for (int i = 0; i < 8; ++i) ctx.coef.p[i] = desc.coef_params[i];
+  MFMG_REQUIRE(desc.coef_kind >= 0 && desc.coef_kind <= 2, MFMG_ERR_INVALID_ARG, "unknown coefficient kind");
   ctx.stream = s;
   ctx.meshes = mesh.gc;
   ctx.max_rhs = desc.max_rhs > 0 ? desc.max_rhs : 1;
@@ -399,7 +402,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
       L.mesh = pairs[l].first;
       L.k = pairs[l].second;
       L.dtype = level_dtype(desc, l);
-      host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false);
+      host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false, -1, &ctx.coef);
       init_level(ctx, L, host[l], ctx.meshes[L.mesh].lo, true, s);
     }
     for (int l = 1; l < nl; ++l) {

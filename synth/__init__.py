@@ -60,8 +60,11 @@ def coef_desc(kind, params):
 
 
 # a high-contrast inclusion: c = 1000 in the ball of radius 0.3 about
-# (0.5, 0.5, 0.5), 1 elsewhere (the benchmark's coefficient workload)
+# (0.5, 0.5, 0.5), 1 elsewhere
 COEF_INCLUSION = coef_desc(COEF_BALL, (0.5, 0.5, 0.5, 0.3, 1000.0, 1.0))
+# a high-contrast checkerboard of 0.25-cubes (c = 1 and 1000), aligned with the
+# coarse grids of the benchmark meshes
+COEF_CHECKER_1000 = coef_desc(COEF_CHECKER, (1.0, 1000.0, 0.25, 0.0))
 
 
 def mesh_desc(name, n0, lo, hi, n_global, steps):
