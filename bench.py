@@ -422,12 +422,12 @@ def main():
                                        "residual": st["final_residual"], "levels": shp.n_levels,
                                        "setup_s": round(setup_hp, 2)}
         del shp
-        # -div(c grad u), c constant per cell: a 1:1000 checkerboard of 0.25-cubes
-        # (aligned with every level's cells), and a c = 1000 ball inclusion
-        # (radius 0.3 about the centre), whose boundary each rediscretised
-        # level resolves differently; the latter is capped at 100 iterations
+        # -div(c grad u), c constant per cell (coarser levels average it over the
+        # leaves): a 1:1000 checkerboard of 0.25-cubes (aligned with every
+        # level's cells), and a c = 1000 ball inclusion of radius 0.3 about the
+        # centre, whose boundary no level resolves exactly
         for name, co, cap in (("cube16_q4_checker1000_fp64", synth.COEF_CHECKER_1000, 200),
-                              ("cube16_q4_inclusion1000_fp64", synth.COEF_INCLUSION, 100)):
+                              ("cube16_q4_inclusion1000_fp64", synth.COEF_INCLUSION, 200)):
             torch.cuda.empty_cache()
             t0 = time.time()
             sco = mfmg.Solver(mesh, k, mfmg.SCHEME_H_THEN_P, coef=co)

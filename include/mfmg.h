@@ -133,8 +133,11 @@ typedef struct {
                             outlook); 0 = none.  The new coarsest level must
                             have at most 12000 DoFs. */
   int coef_kind;         /* diffusion coefficient c of -div(c grad u), constant
-                            per cell: c at the cell centre rounded to
-                            bfloat16, on every level's own cells.  0: c =
+                            per cell and rounded to bfloat16: a leaf of the
+                            finest mesh takes c at its centre, a refined cell
+                            of a coarser level the mean of its 8 children's
+                            values (the average over the finest leaves it
+                            covers).  0: c =
                             coef_params[0] (0 -> 1); 1: coef_params[4] inside
                             the ball |x - p[0..2]| <= p[3], else p[5]; 2:
                             checkerboard of cubes of edge p[2] anchored at

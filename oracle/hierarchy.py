@@ -56,7 +56,7 @@ class Hierarchy:
 
     def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0, coef=None):
         self.pairs = level_pairs(tree, k, scheme)[drop_coarse:]
-        self.spaces = [Space(m, d, dirichlet=dirichlet, coef=coef) for m, d in self.pairs]
+        self.spaces = [Space(m, d, dirichlet=dirichlet, coef=coef, coef_fine=tree) for m, d in self.pairs]
         self.levels = []
         for l, S in enumerate(self.spaces):
             A = assemble_stiffness(S)

@@ -37,7 +37,7 @@ import numpy as np
 from . import fe, octree, solvers
 from .hierarchy import degree_sequence
 from .octree import _unpack3, pack
-from .space import Space, assemble_stiffness, coefficient, prolongation
+from .space import CellCoefficient, Space, assemble_stiffness, prolongation
 
 
 class _LevelIndex:
@@ -58,7 +58,7 @@ class LevelSpace(Space):
 
     def __init__(self, tree, level, k, coef=None):
         self.tree = tree
-        self.coef = coefficient(coef) if coef is not None else None
+        self.coef = CellCoefficient(coef, tree) if coef is not None else None
         self.level = int(level)
         self.k = int(k)
         self.n = self.k + 1
@@ -172,7 +172,7 @@ class LSHierarchy:
         self.spaces = [LevelSpace(tree, l, k, coef) for l in level_numbers(tree)]
         if coarse_p:
             grid = octree.gc_sequence(tree)[-1]
-            self.spaces = [Space(grid, d, coef=coef) for d in degree_sequence(k)[:0:-1]] + self.spaces
+            self.spaces = [Space(grid, d, coef=coef, coef_fine=tree) for d in degree_sequence(k)[:0:-1]] + self.spaces
         self.levels = []
         for l, V in enumerate(self.spaces):
             P = prolongation(V, self.spaces[l - 1]) if l > 0 else None

@@ -71,15 +71,46 @@ def code1d(l, i, a, k):
     return 2 * ((((l << 25) + i) * 16) + a) + 1
 
 
+class CellCoefficient:
+    """Cell values of a coefficient descriptor on the cells of a multigrid
+    hierarchy built over the finest mesh ``fine``: a leaf of ``fine`` takes
+    c at its centre; a refined cell takes the mean of its eight children's
+    values (the volume average over the leaves it covers), so that coarse
+    levels see the fine coefficient averaged rather than sampled.  The value
+    used by the operator is this number rounded to bfloat16."""
+
+    def __init__(self, desc, fine):
+        self.c = coefficient(desc)
+        self.fine = fine
+        self.refined = [set(r.tolist()) for r in fine.refined]
+        self.memo = {}
+
+    def raw(self, cell):
+        v = self.memo.get(cell)
+        if v is None:
+            l, i, j, m = cell
+            if l < len(self.refined) and ((i << 42) | (j << 21) | m) in self.refined[l]:
+                v = sum(self.raw((l + 1, 2 * i + a, 2 * j + b, 2 * m + c))
+                        for c in (0, 1) for b in (0, 1) for a in (0, 1)) / 8.0
+            else:
+                h = self.fine.h(l)
+                v = self.c(self.fine.lo + h * (np.array([i, j, m], float) + 0.5))
+            self.memo[cell] = v
+        return v
+
+    def __call__(self, cell):
+        return bf16_round(self.raw(cell))
+
+
 class Space:
     """Q_k on the leaves of ``tree``; homogeneous Dirichlet on the boundary.
     ``coef``: a coefficient descriptor (None: c = 1); the operator is then
-    -div(c grad u) with c constant per cell, its value at the cell centre
-    rounded to bfloat16."""
+    -div(c grad u) with c constant per cell (``CellCoefficient`` over the
+    finest mesh ``coef_fine``, by default ``tree`` itself)."""
 
-    def __init__(self, tree, k, dirichlet=True, build=True, coef=None):
+    def __init__(self, tree, k, dirichlet=True, build=True, coef=None, coef_fine=None):
         self.tree = tree
-        self.coef = coefficient(coef) if coef is not None else None
+        self.coef = CellCoefficient(coef, coef_fine if coef_fine is not None else tree) if coef is not None else None
         self.k = int(k)
         self.n = self.k + 1
         self.dirichlet = dirichlet
@@ -223,12 +254,7 @@ class Space:
         return self.tree.h(cell[0])
 
     def cell_coef(self, cell):
-        if self.coef is None:
-            return 1.0
-        l, i, j, m = cell
-        h = self.tree.h(l)
-        centre = self.tree.lo + h * (np.array([i, j, m], float) + 0.5)
-        return bf16_round(self.coef(centre))
+        return 1.0 if self.coef is None else self.coef(cell)
 
     def local_constraint_matrix(self, cell):
         """(global ids, dense C_e of shape (n^3, m))."""

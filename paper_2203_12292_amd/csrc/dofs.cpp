@@ -93,6 +93,21 @@ double CoefDesc::value(double x, double y, double z) const {
   }
 }
 
+namespace {
+// cell value of the coefficient over the finest mesh (children summed in the
+// order x fastest, then divided by 8)
+double cell_coef(const CoefDesc& cd, const Octree& fine, int l, int64_t i, int64_t j, int64_t k) {
+  if (fine.is_refined(l, i, j, k)) {
+    double s = 0.0;
+    for (int ch = 0; ch < 8; ++ch)
+      s += cell_coef(cd, fine, l + 1, 2 * i + (ch & 1), 2 * j + ((ch >> 1) & 1), 2 * k + ((ch >> 2) & 1));
+    return s / 8.0;
+  }
+  const double h = fine.h(l);
+  return cd.value(fine.lo + (i + 0.5) * h, fine.lo + (j + 0.5) * h, fine.lo + (k + 0.5) * h);
+}
+}  // namespace
+
 uint32_t coef_mask_bits(double c) {
   MFMG_REQUIRE(c >= 1e-30 && c <= 1e30, MFMG_ERR_INVALID_ARG, "the coefficient must lie in [1e-30, 1e30]");
   int e = 0;
@@ -104,7 +119,7 @@ uint32_t coef_mask_bits(double c) {
 }
 
 LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes, int only_level,
-                           const CoefDesc* coef) {
+                           const CoefDesc* coef, const Octree* coef_fine) {
   MFMG_REQUIRE(k >= 1 && k <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   LevelDofs L;
   L.k = k;
@@ -172,11 +187,7 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
           m |= 1u << (MASK_EDGE_SHIFT + d);
       }
     }
-    {
-      const double h = tree.h(x.level);
-      const double xc = tree.lo + (x.i + 0.5) * h, yc = tree.lo + (x.j + 0.5) * h, zc = tree.lo + (x.k + 0.5) * h;
-      m |= coef_mask_bits(coef ? coef->value(xc, yc, zc) : 1.0);
-    }
+    m |= coef_mask_bits(coef ? cell_coef(*coef, coef_fine ? *coef_fine : tree, x.level, x.i, x.j, x.k) : 1.0);
     L.mask[c] = m;
     if (mask_hanging(m)) ++L.n_hanging_cells;
   }

@@ -88,8 +88,11 @@ struct LevelDofs {
 };
 
 // Scalar diffusion coefficient c(x) of the operator -div(c grad u), taken
-// constant per cell: its value at the cell centre rounded to bfloat16 (the
-// form in which the cell mask carries it).  kind 0: c = p[0] (0 -> 1);
+// constant per cell.  A leaf of the finest mesh takes c at its centre; a
+// refined cell (on a coarser multigrid level) the mean of its eight
+// children's values, i.e. the average over the finest leaves it covers.  The
+// operator uses this value rounded to bfloat16 (the form in which the cell
+// mask carries it).  kind 0: c = p[0] (0 -> 1);
 // kind 1: p[4] inside the ball |x - (p[0],p[1],p[2])| <= p[3], else p[5];
 // kind 2: checkerboard of cubes of edge p[2] anchored at (p[3],p[3],p[3]),
 // p[0] on even and p[1] on odd cubes.
@@ -107,8 +110,9 @@ uint32_t coef_mask_bits(double c);
 // local-smoothing level, Section 2.1: a conforming mesh of the region they
 // cover, without hanging nodes); DoFs on the boundary of that region inside
 // the domain are flagged as refinement-edge DoFs.
+// `coef_fine` is the finest mesh of the hierarchy (NULL: `tree`).
 LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool codes = true, int only_level = -1,
-                           const CoefDesc* coef = nullptr);
+                           const CoefDesc* coef = nullptr, const Octree* coef_fine = nullptr);
 
 // Transfer data between a fine level and the next coarser one (Section 3.5).
 // Geometric: every coarse cell is a fine cell (identity category) or the

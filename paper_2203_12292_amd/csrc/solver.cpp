@@ -325,8 +325,8 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
     L.dtype = level_dtype(desc, l);
     MFMG_REQUIRE(L.dtype == ctx.levels[0].dtype, MFMG_ERR_UNSUPPORTED,
                  "local smoothing needs one storage type on all levels");
-    host[l] = poly_level ? build_level_dofs(ctx.meshes[0], L.k, true, false, -1, &ctx.coef)
-                         : build_level_dofs(tree, L.k, true, false, L.only_level, &ctx.coef);
+    host[l] = poly_level ? build_level_dofs(ctx.meshes[0], L.k, true, false, -1, &ctx.coef, &tree)
+                         : build_level_dofs(tree, L.k, true, false, L.only_level, &ctx.coef, &tree);
     MFMG_REQUIRE(l > np || host[l].n_edge_dofs == 0, MFMG_ERR_INVALID_ARG, "the coarse grid has an edge");
     init_level(ctx, L, host[l], tree.lo, true, s);
     L.n_edge = host[l].n_edge_dofs;
@@ -402,7 +402,8 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
       L.mesh = pairs[l].first;
       L.k = pairs[l].second;
       L.dtype = level_dtype(desc, l);
-      host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false, -1, &ctx.coef);
+      host[l] = build_level_dofs(ctx.meshes[L.mesh], L.k, desc.dirichlet != 0, false, -1, &ctx.coef,
+                                 &ctx.meshes.back());
       init_level(ctx, L, host[l], ctx.meshes[L.mesh].lo, true, s);
     }
     for (int l = 1; l < nl; ++l) {

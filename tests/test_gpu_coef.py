@@ -1,8 +1,9 @@
 """GPU parity of the operator -div(c grad u) with a diffusion coefficient that
-is constant per cell (its value at the cell centre, rounded to bfloat16, as
-the cell mask carries it), against the FP64 oracle: operator, diagonal and
-solves on every level scheme, with a high-contrast inclusion and a
-checkerboard.  Tolerances as for the Laplacian.
+is constant per cell (c at a leaf's centre, the mean over the leaves a
+coarser cell covers, rounded to bfloat16 as the cell mask carries it),
+against the FP64 oracle: operator, diagonal and solves on every level
+scheme, with high-contrast inclusions and a checkerboard.  Tolerances as for
+the Laplacian.
 """
 import functools
 
@@ -23,9 +24,7 @@ DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
 TOL = {torch.float64: 1e-12, torch.float32: 2e-5}
 COEFS = {
     "inclusion": synth.COEF_INCLUSION,
-    # an inclusion that the 2^3 and 4^3 coarse grids resolve (a coarse cell
-    # centre lies inside it): every level evaluates c at its own cell
-    # centres, so an inclusion the coarse grid misses slows the V-cycle down
+    # an inclusion around a coarse cell centre of the 2^3 and 4^3 grids
     "corner_inclusion": synth.coef_desc(synth.COEF_BALL, (0.25, 0.25, 0.25, 0.3, 1000.0, 1.0)),
     "checker": synth.coef_desc(synth.COEF_CHECKER, (1.0, 0.01, 0.25, 0.0)),
 }
@@ -81,8 +80,9 @@ def test_operator_and_diagonal(name, k, coef, dtype):
 
 
 @pytest.mark.parametrize("name,k,scheme,coef", [("tiny", 2, "h", "corner_inclusion"),
-                                                ("small", 4, "h_then_p", "corner_inclusion"),
-                                                ("small", 4, "ls", "corner_inclusion"), ("cfg1", 2, "h", "inclusion")])
+                                                ("small", 4, "h_then_p", "inclusion"),
+                                                ("small", 4, "ls", "corner_inclusion"), ("cfg1", 2, "h", "inclusion"),
+                                                ("small", 4, "ls", "inclusion")])
 def test_vcycle_and_solve(name, k, scheme, coef):
     H, S, P = pair(name, k, scheme, coef)
     levels = H.levels
