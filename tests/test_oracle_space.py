@@ -15,7 +15,7 @@ import pytest
 
 import synth
 from oracle import fe, octree, solvers
-from oracle.space import (Space, assemble_load, assemble_stiffness, distribute_values,
+from oracle.space import (Space, assemble_load, assemble_stiffness, coefficient, distribute_values,
                           l2_error, prolongation)
 
 
@@ -187,3 +187,18 @@ def test_cellwise_coefficient_energy_of_linear_functions(small, k):
     S4 = Space(small, k, coef=synth.coef_desc(synth.COEF_CONST, (4.0,)))
     S1 = Space(small, k)
     assert np.abs((assemble_stiffness(S4) - 4.0 * assemble_stiffness(S1)).toarray()).max() == 0.0
+
+
+def test_coarse_cell_coefficient_is_the_leaf_average():
+    """A coarser level's cell coefficient (before rounding) is the volume
+    average over the finest leaves it covers: summed over any coarse mesh of
+    the hierarchy, c_K |K| reproduces the fine integral of the coefficient."""
+    from oracle.space import CellCoefficient
+    fine = octree.build_mesh(synth.small_mesh())
+    cc = CellCoefficient(synth.COEF_INCLUSION, fine)
+    c = coefficient(synth.COEF_INCLUSION)
+    total = sum(c(fine.lo + fine.h(l) * (ijk + 0.5)) * fine.h(l) ** 3
+                for l, cells in fine.all_leaves() for ijk in cells.astype(float))
+    for mesh in octree.gc_sequence(fine)[1:]:
+        coarse = sum(cc.raw((l, *map(int, ijk))) * mesh.h(l) ** 3 for l, cells in mesh.all_leaves() for ijk in cells)
+        assert abs(coarse - total) <= 1e-12 * total
