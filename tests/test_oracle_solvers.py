@@ -96,10 +96,10 @@ def test_early_coarse_switch(drop):
     """The direct coarse solve on a finer level (with hanging nodes) still gives
     a symmetric positive definite V-cycle, and PCG reaches the direct solution
     in no more iterations than with the full hierarchy."""
-    from helpers import oracle_tree
+    from helpers import oracle_hierarchy, oracle_tree
     tree = oracle_tree("cfg1")
     H = Hierarchy(tree, 2, "h", drop_coarse=drop)
-    full = Hierarchy(tree, 2, "h")
+    full = oracle_hierarchy("cfg1", 2)
     assert len(H.levels) == len(full.levels) - drop
     assert any(H.spaces[0].cell_has_hanging(c) for c in H.spaces[0].cells)
     rng = np.random.default_rng(21)
