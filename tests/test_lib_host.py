@@ -40,6 +40,39 @@ def test_invalid_arguments_are_rejected():
     assert L.mfmg_host_level_matrix(m.handle, 99, 2, 1, ctypes.byref(n), None, None) == -1
 
 
+def test_level_options_are_checked_before_any_device_work():
+    """Set-up options that cannot work are refused on the host: an unknown
+    coefficient kind, leaving out every level, local smoothing without
+    Dirichlet conditions or with an early coarse switch, a non-positive
+    coefficient (bfloat16 encoding), and a local-smoothing level that does
+    not exist."""
+    L = mfmg.lib()
+    m = mfmg.Mesh(synth.CFG1_TINY)
+    h = ctypes.c_void_p()
+
+    def setup(**kw):
+        d = mfmg.LevelDesc()
+        d.degree, d.scheme, d.dirichlet = kw.get("degree", 2), kw.get("scheme", mfmg.SCHEME_H), kw.get("dirichlet", 1)
+        d.drop_coarse, d.coef_kind = kw.get("drop", 0), kw.get("coef_kind", 0)
+        for i, v in enumerate(kw.get("coef_params", ())):
+            d.coef_params[i] = v
+        code = L.mfmg_setup_levels(m.handle, ctypes.byref(d), None, ctypes.byref(h))
+        return code, L.mfmg_last_error().decode()
+
+    assert setup(coef_kind=7) == (mfmg.ERR_INVALID_ARG, "unknown coefficient kind")
+    code, msg = setup(drop=3)
+    assert code == mfmg.ERR_INVALID_ARG and "drop_coarse" in msg
+    code, msg = setup(scheme=mfmg.SCHEME_LS, dirichlet=0)
+    assert code == mfmg.ERR_UNSUPPORTED and "Dirichlet" in msg
+    code, msg = setup(scheme=mfmg.SCHEME_LS_THEN_P, drop=1)
+    assert code == mfmg.ERR_UNSUPPORTED and "covers the domain" in msg
+    code, msg = setup(coef_kind=1, coef_params=(0.5, 0.5, 0.5, 0.3, -5.0, 1.0))
+    assert code == mfmg.ERR_INVALID_ARG and "coefficient" in msg
+    n, q = ctypes.c_int64(), ctypes.c_int64()
+    assert L.mfmg_host_ls_level(m.handle, 9, 2, ctypes.byref(n), ctypes.byref(q), None, None, None, None,
+                                None) == mfmg.ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("case", ["octant", "shell"])
 def test_mesh_counts_match_paper(case):
     g = GOLD[case]
