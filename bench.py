@@ -449,8 +449,12 @@ def main():
                 "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
                 "levels": s1.n_levels, "coarse_dofs": s1.n_dofs(0)}
             del s1
-        for name, dts in (("cube4_q2_fp64", []), ("cube4_q2_mixed_bf16", [mfmg.BF16, mfmg.BF16, mfmg.F32])):
-            s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, level_dtypes=dts)
+        for name, dts, graph in (("cube4_q2_fp64", [], False),
+                                 ("cube4_q2_mixed_bf16", [mfmg.BF16, mfmg.BF16, mfmg.F32], False),
+                                 ("cube4_q2_fp64_graph", [], True),
+                                 ("cube4_q2_mixed_bf16_graph", [mfmg.BF16, mfmg.BF16, mfmg.F32], True)):
+            # (graph: the V-cycles of the solve replayed from a HIP graph)
+            s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H, level_dtypes=dts, graph_vcycle=graph)
             b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
             s1.rhs(b1)
             x1 = torch.zeros_like(b1)

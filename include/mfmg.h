@@ -145,6 +145,12 @@ typedef struct {
                             cubes.  c must lie in [1e-30, 1e30].  The load
                             vector (mfmg_rhs) does not depend on c. */
   double coef_params[8];
+  int graph_vcycle;      /* 1: mfmg_solve replays its V-cycles from a HIP graph
+                            (captured once per vector pair on a private
+                            stream after a first eager cycle; fewer launches
+                            for small levels).  The learned coarse
+                            correction and the recording of coarse
+                            right-hand sides keep the eager path.  0 = eager. */
 } mfmg_level_desc;
 
 typedef struct {

@@ -64,8 +64,30 @@ struct NetState {
   DeviceArray<float> X, T, z1, h1, z2, h2, y, d3, d2, d1, lossbuf;
 };
 
+// V-cycles of the outer solver replayed from HIP graphs, one per (x, b,
+// n_vec); captured on a private stream of default priority.
+struct GraphCache {
+  struct Entry {
+    const void* x;
+    const void* b;
+    int nv;
+    hipGraphExec_t exec;
+  };
+  std::vector<Entry> entries;
+  std::vector<std::pair<const void*, const void*>> seen;  // pairs run eagerly once
+  hipStream_t capture = nullptr;
+  GraphCache() = default;
+  GraphCache(const GraphCache&) = delete;
+  GraphCache& operator=(const GraphCache&) = delete;
+  ~GraphCache() {
+    for (auto& e : entries) (void)hipGraphExecDestroy(e.exec);
+    if (capture) (void)hipStreamDestroy(capture);
+  }
+};
+
 struct Context {
   mfmg_level_desc desc{};
+  GraphCache graphs;
   CoefDesc coef;  // diffusion coefficient (constant per cell)
   std::vector<Octree> meshes;
   std::vector<Level> levels;  // 0 = coarsest

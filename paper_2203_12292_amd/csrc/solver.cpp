@@ -675,6 +675,48 @@ void vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s) {
   launch_cast(F.dtype, MFMG_F64, n, F.x.ptr, x, s);  // copy_from_mg
 }
 
+namespace {
+// One V-cycle for the outer solver: eager, or replayed from a graph captured
+// for this (x, b, n_vec) after a first eager run (which also initialises the
+// launchers' one-time state outside the capture).
+void solver_vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t s) {
+  const NetState& N = ctx.net;
+  if (!ctx.desc.graph_vcycle || N.mode != MFMG_COARSE_EXACT || N.rec_count < N.rec_capacity) {
+    vcycle(ctx, nv, x, b, s);
+    return;
+  }
+  GraphCache& G = ctx.graphs;
+  for (const auto& e : G.entries)
+    if (e.x == x && e.b == b && e.nv == nv) {
+      MFMG_HIP(hipGraphLaunch(e.exec, s));
+      return;
+    }
+  const auto key = std::make_pair(static_cast<const void*>(x), static_cast<const void*>(b));
+  if (std::find(G.seen.begin(), G.seen.end(), key) == G.seen.end()) {
+    G.seen.push_back(key);
+    vcycle(ctx, nv, x, b, s);
+    return;
+  }
+  if (!G.capture) MFMG_HIP(hipStreamCreateWithFlags(&G.capture, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  MFMG_HIP(hipStreamBeginCapture(G.capture, hipStreamCaptureModeThreadLocal));
+  try {
+    vcycle(ctx, nv, x, b, G.capture);
+  } catch (...) {
+    (void)hipStreamEndCapture(G.capture, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  MFMG_HIP(hipStreamEndCapture(G.capture, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  MFMG_HIP(err);
+  G.entries.push_back({x, b, nv, exec});
+  MFMG_HIP(hipGraphLaunch(exec, s));
+}
+}  // namespace
+
 int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,
         mfmg_solve_stats* stats, hipStream_t s) {
   MFMG_REQUIRE(nv >= 1 && nv <= ctx.max_rhs, MFMG_ERR_INVALID_ARG, "n_vec exceeds max_rhs");
@@ -712,7 +754,7 @@ int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_i
   if (all_zero) {
     status = MFMG_OK;
   } else {
-    vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
+    solver_vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
     MFMG_HIP(hipMemcpyAsync(ctx.cg_p.ptr, ctx.cg_z.ptr, nn * 8, hipMemcpyDeviceToDevice, s));
     launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_z.ptr, ctx.cg_partial.ptr, rz, s);
     for (it = 1; it <= max_it; ++it) {
@@ -736,7 +778,7 @@ int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_i
       if (worst <= rtol) { status = MFMG_OK; break; }
       if (breakdown) { status = MFMG_ERR_BREAKDOWN; break; }
       if (flexible) std::swap(ctx.cg_z.ptr, ctx.cg_zold.ptr);
-      vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
+      solver_vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
       launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_z.ptr, ctx.cg_partial.ptr, rzn, s);
       if (flexible) launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_zold.ptr, ctx.cg_partial.ptr, rzo, s);
       launch_cg_update_p(n, nv, rzn, flexible ? rzo : nullptr, rz, ctx.cg_z.ptr, ctx.cg_p.ptr, s);
