@@ -151,6 +151,10 @@ typedef struct {
                             for small levels).  The learned coarse
                             correction and the recording of coarse
                             right-hand sides keep the eager path.  0 = eager. */
+  int fmg_start;         /* 1: mfmg_solve starts from one full-multigrid pass
+                            (mfmg_fmg, one V-cycle per level) instead of
+                            x0 = 0; the stopping rule stays relative to
+                            ||b||.  Global-coarsening schemes only. */
 } mfmg_level_desc;
 
 typedef struct {

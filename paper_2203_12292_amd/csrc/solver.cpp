@@ -376,6 +376,8 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   ctx.coef.kind = desc.coef_kind;
   for (int i = 0; i < 8; ++i) ctx.coef.p[i] = desc.coef_params[i];
   MFMG_REQUIRE(desc.coef_kind >= 0 && desc.coef_kind <= 2, MFMG_ERR_INVALID_ARG, "unknown coefficient kind");
+  MFMG_REQUIRE(!desc.fmg_start || (desc.scheme != MFMG_SCHEME_LS && desc.scheme != MFMG_SCHEME_LS_THEN_P),
+               MFMG_ERR_UNSUPPORTED, "full multigrid runs on global-coarsening levels");
   ctx.stream = s;
   ctx.meshes = mesh.gc;
   ctx.max_rhs = desc.max_rhs > 0 ? desc.max_rhs : 1;
@@ -754,6 +756,17 @@ int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_i
   if (all_zero) {
     status = MFMG_OK;
   } else {
+    if (ctx.desc.fmg_start) {  // x0 from one full-multigrid pass, r0 = b - A x0
+      fmg(ctx, nv, x, b, 1, s);
+      launch_vmult(F.view, MFMG_F64, nv, ctx.cg_q.ptr, x, s);
+      launch_residual_update(MFMG_F64, nn, b, ctx.cg_q.ptr, ctx.cg_r.ptr, s);
+      launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_r.ptr, ctx.cg_partial.ptr, rr, s);
+      MFMG_HIP(hipMemcpyAsync(hr.data(), rr, nv * 8, hipMemcpyDeviceToHost, s));
+      sync(s);
+      double w0 = 0.0;
+      for (int v = 0; v < nv; ++v) w0 = std::max(w0, hb[v] > 0 ? std::sqrt(hr[v]) / hb[v] : 0.0);
+      if (stats) stats->residual_history[0] = w0;
+    }
     solver_vcycle(ctx, nv, ctx.cg_z.ptr, ctx.cg_r.ptr, s);
     MFMG_HIP(hipMemcpyAsync(ctx.cg_p.ptr, ctx.cg_z.ptr, nn * 8, hipMemcpyDeviceToDevice, s));
     launch_dot(n, nv, ctx.cg_r.ptr, ctx.cg_z.ptr, ctx.cg_partial.ptr, rz, s);
