@@ -137,13 +137,15 @@ typedef struct {
                             finest mesh takes c at its centre, a refined cell
                             of a coarser level the mean of its 8 children's
                             values (the average over the finest leaves it
-                            covers).  0: c =
-                            coef_params[0] (0 -> 1); 1: coef_params[4] inside
-                            the ball |x - p[0..2]| <= p[3], else p[5]; 2:
-                            checkerboard of cubes of edge p[2] anchored at
-                            (p[3],p[3],p[3]), p[0] on even and p[1] on odd
-                            cubes.  c must lie in [1e-30, 1e30].  The load
-                            vector (mfmg_rhs) does not depend on c. */
+                            covers).  With p = coef_params:
+                            0: c = p[0] (0 -> 1);
+                            1: p[4] inside the ball |x - p[0..2]| <= p[3],
+                               else p[5];
+                            2: checkerboard of cubes of edge p[2] anchored
+                               at (p[3],p[3],p[3]), p[0] on even and p[1]
+                               on odd cubes.
+                            c must lie in [1e-30, 1e30].  The load vector
+                            (mfmg_rhs) does not depend on c. */
   double coef_params[8];
   int graph_vcycle;      /* 1: mfmg_solve replays its V-cycles from a HIP graph
                             (captured once per vector pair on a private
