@@ -26,9 +26,10 @@
  *    [async] only enqueue work on it; the others synchronise it.
  *  - The library owns mesh and level data; it allocates device memory in
  *    mfmg_setup_levels (metadata, per-level work vectors) and frees it in
- *    mfmg_destroy_ctx.  The calls below allocate nothing else, except
- *    mfmg_solve / mfmg_vcycle for n_vec > max_rhs (rejected) and the learned
- *    correction set-up.
+ *    mfmg_destroy_ctx.  The calls below allocate nothing else, except the
+ *    learned correction's recording and training (mfmg_net_record,
+ *    mfmg_net_loss_grad, mfmg_net_train) and mfmg_rhs when its parameters
+ *    exceed 8 Gaussians per vector (the staging buffer then grows once).
  */
 #ifndef MFMG_H
 #define MFMG_H
@@ -350,7 +351,9 @@ int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk);
  * prediction: if ||b0 - A0 y||_2 > tau ||b0||_2 the exact solution is used.
  * Flat FP32 parameters: W1 ((nq+3) x 64, row-major), b1, W2 (64x64), b2,
  * W3 (64 x nq), b3, nq = (k+1)^3 of level 0.  Requires a coarse level
- * without hanging nodes and at most 2048 DoFs. */
+ * without hanging nodes, at most 2048 DoFs and nq + 3 <= 64 (degree <= 2);
+ * otherwise every mfmg_net_* call except mfmg_net_mode(EXACT) returns
+ * MFMG_ERR_UNSUPPORTED. */
 enum { MFMG_COARSE_EXACT = 0, MFMG_COARSE_LEARNED = 1, MFMG_COARSE_ZERO = 2 };
 
 typedef struct {
@@ -376,6 +379,16 @@ int mfmg_net_loss_grad(mfmg_ctx ctx, int n_rows, const float* X, const float* T,
  * history (host, `epochs` floats, may be NULL) gets the data-set loss after
  * each epoch.  Synchronous. */
 int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history);
+/* [async] y = the network's coarse correction for the level-0 right-hand
+ * side b, without the residual check: per coarse cell, the MLP maps
+ * (b at the cell's nodes / s, cell centre) to nodal values; y_i is s times the
+ * mean of the values of the cells that have DoF i as a node, s = ||b||_2
+ * (y = 0 for b = 0).  b and y are level-0 vectors of `dtype` (the level's
+ * storage type or any other), n0 entries each, caller-owned device memory;
+ * the network arithmetic is FP32, the averaging FP64.  Uses the library's
+ * inference work space: calls on one context must not overlap.  Needs the
+ * network (MFMG_ERR_UNSUPPORTED otherwise). */
+int mfmg_net_infer(mfmg_ctx ctx, int dtype, void* y, const void* b, void* stream);
 /* Coarse solver of the V-cycle: MFMG_COARSE_EXACT, _LEARNED (with residual check and
  * fallback, threshold tau) or _ZERO (no coarse correction; for comparison). */
 int mfmg_net_mode(mfmg_ctx ctx, int mode, double tau);

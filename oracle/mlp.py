@@ -50,9 +50,16 @@ def gelu_prime(z):
     return 0.5 * (1.0 + erf(z / np.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)
 
 
+def sizes_for(nin):
+    """Layer widths for nin inputs: the nq = nin - 3 node values and 3 centre
+    coordinates in, two hidden layers of 64, nq outputs."""
+    return (nin, 64, 64, nin - 3)
+
+
 def forward(theta, X):
-    """Y (rows x 27) and the cache of pre-activations."""
-    (W1, b1), (W2, b2), (W3, b3) = unpack(theta)
+    """Y (rows x nq) and the cache of pre-activations (nq = X.shape[1] - 3)."""
+    X = np.asarray(X, dtype=np.float64)
+    (W1, b1), (W2, b2), (W3, b3) = unpack(theta, sizes_for(X.shape[1]))
     Z1 = X @ W1 + b1
     H1 = gelu(Z1)
     Z2 = H1 @ W2 + b2
@@ -69,7 +76,7 @@ def loss(theta, X, T):
 
 def loss_and_grad(theta, X, T):
     """Loss and its gradient w.r.t. theta (reverse-mode chain rule)."""
-    (W1, b1), (W2, b2), (W3, b3) = unpack(theta)
+    (W1, b1), (W2, b2), (W3, b3) = unpack(theta, sizes_for(np.shape(X)[1]))
     Y, (X, Z1, H1, Z2, H2) = forward(theta, X)
     n = Y.size
     D3 = 2.0 * (Y - T) / n
@@ -112,3 +119,39 @@ def init_params(seed=0, sizes=SIZES):
         parts.append(rng.standard_normal(a * b) * np.sqrt(2.0 / a))
         parts.append(np.zeros(b))
     return np.concatenate(parts)
+
+
+def coarse_correction(theta, space, b):
+    """The network's coarse correction y for the right-hand side b of the
+    coarse space ``space`` (a conforming mesh: no hanging nodes).
+
+    With s = ||b||_2, each leaf cell is one row of the network: inputs the
+    values of b at the cell's (k+1)^3 nodes (x fastest; 0 at Dirichlet nodes)
+    divided by s, then the cell centre; outputs the cell's nodal correction
+    divided by s.  A DoF takes s times the mean of the outputs of the cells
+    that have it as a node.  b = 0 gives y = 0.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    s = float(np.linalg.norm(b))
+    y = np.zeros(space.n_dofs)
+    if s == 0.0:
+        return y
+    count = np.zeros(space.n_dofs)
+    for cell in space.cells:
+        ids = []
+        for row in space.cell_rows(cell):
+            if not row:
+                ids.append(-1)  # Dirichlet node
+                continue
+            assert len(row) == 1 and row[0][1] == 1.0, "coarse space with hanging nodes"
+            ids.append(space.key_index[row[0][0]])
+        ids = np.array(ids)
+        l, i, j, m = cell
+        centre = space.tree.lo + space.tree.h(l) * (np.array([i, j, m], float) + 0.5)
+        x = np.concatenate([np.where(ids >= 0, b[np.maximum(ids, 0)], 0.0) / s, centre])
+        out = forward(theta, x[None, :])[0][0]
+        for q, g in enumerate(ids):
+            if g >= 0:
+                y[g] += out[q]
+                count[g] += 1.0
+    return s * y / count

@@ -441,8 +441,10 @@ int mfmg_rhs(mfmg_ctx ctx, int level, int kind, const double* params, int n_term
     check_vec(b_f64, L.n_dofs, "b");
     if (L.n_dofs == 0) return MFMG_OK;
     const size_t np = kind == MFMG_RHS_CONST ? 1 : kind == MFMG_RHS_SINE ? 2 : static_cast<size_t>(n_terms) * 5 * n_vec;
-    mfmg::DeviceArray<double> dp;
-    dp.upload(params, np);
+    mfmg::DeviceArray<double>& dp = ctx->ctx.rhs_params;
+    MFMG_HIP(hipStreamSynchronize(as_stream(stream)));  // a previous load may still read dp
+    if (dp.n < np) dp.alloc(np);
+    MFMG_HIP(hipMemcpyAsync(dp.ptr, params, np * sizeof(double), hipMemcpyHostToDevice, as_stream(stream)));
     mfmg::launch_rhs(L.view, kind, dp.ptr, kind == MFMG_RHS_GAUSS ? n_terms : 0, n_vec,
                      static_cast<double*>(b_f64), as_stream(stream));
     MFMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -474,7 +476,8 @@ int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk) {
 
 static void require_net(mfmg::Context& c) {
   MFMG_REQUIRE(c.net.n_params > 0, MFMG_ERR_UNSUPPORTED,
-               "learned coarse correction needs a coarse level without hanging nodes and <= 2048 DoFs");
+               "learned coarse correction needs a coarse level without hanging nodes, <= 2048 DoFs and "
+               "degree <= 2");
 }
 
 int mfmg_net_n_params(mfmg_ctx ctx, int* n) {
@@ -555,6 +558,19 @@ int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history
     MFMG_REQUIRE(desc->epochs >= 1 && desc->batch_rows >= 0, MFMG_ERR_INVALID_ARG, "epochs/batch_rows");
     mfmg::net_train(ctx->ctx, *desc, history, ctx->ctx.stream);
     MFMG_HIP(hipStreamSynchronize(ctx->ctx.stream));
+    return MFMG_OK;
+  });
+}
+
+int mfmg_net_infer(mfmg_ctx ctx, int dtype, void* y, const void* b, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_dtype(dtype);
+    require_net(ctx->ctx);
+    check_vec(y, ctx->ctx.n0, "y");
+    check_vec(b, ctx->ctx.n0, "b");
+    MFMG_REQUIRE(y != b, MFMG_ERR_INVALID_ARG, "y and b must not alias");
+    mfmg::net_predict(ctx->ctx, dtype, y, b, as_stream(stream));
     return MFMG_OK;
   });
 }

@@ -124,4 +124,10 @@ template <> __host__ __device__ inline bf16 store_as<bf16, double>(double v) {
 
 inline size_t dtype_size(int dt) { return dt == MFMG_F64 ? 8 : dt == MFMG_F32 ? 4 : 2; }
 
+// dtype code of a storage type
+template <typename S> constexpr int dtype_of();
+template <> constexpr int dtype_of<double>() { return MFMG_F64; }
+template <> constexpr int dtype_of<float>() { return MFMG_F32; }
+template <> constexpr int dtype_of<bf16>() { return MFMG_BF16; }
+
 }  // namespace mfmg

@@ -73,8 +73,14 @@ struct GraphCache {
     int nv;
     hipGraphExec_t exec;
   };
+  struct Key {
+    const void* x;
+    const void* b;
+    int nv;
+    bool operator==(const Key& o) const { return x == o.x && b == o.b && nv == o.nv; }
+  };
   std::vector<Entry> entries;
-  std::vector<std::pair<const void*, const void*>> seen;  // pairs run eagerly once
+  std::vector<Key> seen;  // (x, b, n_vec) run eagerly once
   hipStream_t capture = nullptr;
   GraphCache() = default;
   GraphCache(const GraphCache&) = delete;
@@ -103,6 +109,9 @@ struct Context {
   DeviceArray<double> coarse_A64;
   NetState net;
   DeviceArray<float> coarse_inv32;
+  // parameters of the load vector (mfmg_rhs), staged from the host; grown
+  // only when a call needs more than any call before
+  DeviceArray<double> rhs_params;
   // FP64 CG work space on the finest level
   DeviceArray<double> cg_r, cg_p, cg_q, cg_z, cg_zold, cg_partial, cg_scalar;
   std::vector<double> host_scalar;

@@ -319,8 +319,13 @@ unsigned blocks_for(int64_t n, int per = 256) {
 
 int net_n_params(int nq) { return (nq + 3) * HID + HID + HID * HID + HID + HID * nq + nq; }
 
+// The kernels stage one row of inputs (nq + 3 values) and the weight blocks
+// in arrays of the hidden width, and run one thread per output node.
+bool net_supported(int k) { return (k + 1) * (k + 1) * (k + 1) + 3 <= HID; }
+
 void net_setup(Context& ctx, const LevelDofs& L0) {
   NetState& N = ctx.net;
+  MFMG_REQUIRE(net_supported(L0.k), MFMG_ERR_UNSUPPORTED, "coarse degree too high for the network width");
   N.nq = (L0.k + 1) * (L0.k + 1) * (L0.k + 1);
   N.n_cells = static_cast<int>(L0.n_cells);
   N.n0 = static_cast<int>(L0.n_dofs);
@@ -488,6 +493,25 @@ static void net_coarse_solve_t(Context& ctx, S* x, const S* b, hipStream_t s) {
   net_check<S><<<1, 256, 0, s>>>(N.n0, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode, b, x, N.work.ptr,
                                  N.counters.ptr, N.relsum.ptr);
   check_launch();
+}
+
+template <typename S>
+static void net_predict_t(Context& ctx, S* y, const S* b, hipStream_t s) {
+  NetState& N = ctx.net;
+  zero_f<<<1, 256, 0, s>>>(2 * static_cast<int64_t>(N.n0), reinterpret_cast<float*>(N.work.ptr + N.n0));
+  net_infer_cells<S><<<N.n_cells, 64, 0, s>>>(N.n0, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
+                                               N.centre.ptr, b, N.work.ptr);
+  check_launch();
+  launch_cast_from_f64(dtype_of<S>(), N.n0, N.work.ptr + N.n0, y, s);
+}
+
+void net_predict(Context& ctx, int dtype, void* y, const void* b, hipStream_t s) {
+  switch (dtype) {
+    case MFMG_F64: net_predict_t<double>(ctx, static_cast<double*>(y), static_cast<const double*>(b), s); break;
+    case MFMG_F32: net_predict_t<float>(ctx, static_cast<float*>(y), static_cast<const float*>(b), s); break;
+    case MFMG_BF16: net_predict_t<bf16>(ctx, static_cast<bf16*>(y), static_cast<const bf16*>(b), s); break;
+    default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
+  }
 }
 
 void net_coarse_solve(Context& ctx, int dtype, void* x, const void* b, hipStream_t s) {

@@ -431,7 +431,8 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     }
   }
   // learned coarse correction (available for small coarse levels without hanging nodes)
-  if (desc.dirichlet && ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0) net_setup(ctx, host[0]);
+  if (desc.dirichlet && ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0 && net_supported(host[0].k))
+    net_setup(ctx, host[0]);
   // PCG work space
   const int64_t nf = ctx.fine().n_dofs * ctx.max_rhs;
   ctx.cg_r.alloc(nf);
@@ -442,6 +443,7 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   ctx.cg_partial.alloc(static_cast<size_t>(dot_partials_needed()) * 8);
   ctx.cg_scalar.alloc(8 * 8);
   ctx.host_scalar.assign(8 * 8, 0.0);
+  ctx.rhs_params.alloc(static_cast<size_t>(5) * 8 * ctx.max_rhs);  // 8 Gaussians per vector
   sync(s);
 }
 
@@ -693,7 +695,7 @@ void solver_vcycle(Context& ctx, int nv, double* x, const double* b, hipStream_t
       MFMG_HIP(hipGraphLaunch(e.exec, s));
       return;
     }
-  const auto key = std::make_pair(static_cast<const void*>(x), static_cast<const void*>(b));
+  const GraphCache::Key key{x, b, nv};
   if (std::find(G.seen.begin(), G.seen.end(), key) == G.seen.end()) {
     G.seen.push_back(key);
     vcycle(ctx, nv, x, b, s);

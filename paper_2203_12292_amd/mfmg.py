@@ -98,6 +98,7 @@ _SIGS = {
     "mfmg_net_get_params": (_I, [_P, C.POINTER(C.c_float), _I]),
     "mfmg_net_loss_grad": (_I, [_P, _I, _P, _P, _P, C.POINTER(C.c_float)]),
     "mfmg_net_train": (_I, [_P, C.POINTER(NetTrainDesc), C.POINTER(C.c_float)]),
+    "mfmg_net_infer": (_I, [_P, _I, _P, _P, _P]),
     "mfmg_net_mode": (_I, [_P, _I, C.c_double]),
     "mfmg_net_counts": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
     "mfmg_destroy_ctx": (None, [_P]),
@@ -151,6 +152,43 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def _vec(t, numel, name, dtype=None, like=None, device=True):
+    """Check a vector argument before it becomes a raw device pointer: a
+    contiguous torch tensor of exactly `numel` elements, of torch dtype
+    `dtype` (or of the dtype of tensor `like`), on the GPU.  The C ABI cannot
+    check the size of device memory, so every wrapper calls this first."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = like.dtype if like is not None else dtype
+    if want is not None and t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {want}")
+    if t.dtype not in (torch.float64, torch.float32, torch.bfloat16):
+        raise TypeError(f"{name}: unsupported dtype {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if device and not t.is_cuda:
+        raise ValueError(f"{name}: tensor must be on the GPU")
+    return t
+
+
+def _vecs(*args):
+    """_vec for several arguments: first every argument's size, dtype and
+    layout, then every argument's device."""
+    for a in args:
+        _vec(*a, device=False)
+    for a in args:
+        _vec(*a)
+
+
+def _f64(name):
+    """torch.float64 (the FP64 vectors of the outer solver), imported lazily"""
+    import torch
+    return torch.float64
 
 
 class Mesh:
@@ -237,6 +275,7 @@ class Solver:
         n = C.c_int()
         _check(lib().mfmg_n_levels(self.handle, C.byref(n)))
         self.n_levels = n.value
+        self._nd = {}
 
     # -- information -----------------------------------------------------------
     def level_info(self, level):
@@ -269,56 +308,93 @@ class Solver:
         return a.value, b.value
 
     # -- hot path (torch tensors on the GPU) -------------------------------------
+    def _n(self, level):
+        if level not in self._nd:
+            self._nd[level] = self.level_info(level)["n_dofs"]
+        return self._nd[level]
+
+    def _nv(self, n_vec):
+        if not 1 <= n_vec <= 8:
+            raise ValueError(f"n_vec must be in [1, 8], got {n_vec}")
+        return n_vec
+
     def vmult(self, level, dst, src, n_vec=1):
+        n = self._n(level) * self._nv(n_vec)
+        _vecs((src, n, "src", None, None), (dst, n, "dst", None, src))
         _check(lib().mfmg_vmult(self.handle, level, _dtype_code(src), n_vec, _ptr(dst), _ptr(src), _stream()))
         return dst
 
     def diagonal(self, level, diag):
+        _vecs((diag, self._n(level), "diag", None, None))
         _check(lib().mfmg_diagonal(self.handle, level, _dtype_code(diag), _ptr(diag), _stream()))
         return diag
 
     def smooth(self, level, x, b, x_is_zero=False, lam=None, n_vec=1):
+        n = self._n(level) * self._nv(n_vec)
+        _vecs((x, n, "x", None, None), (b, n, "b", None, x))
         lp = (C.c_double * 2)(*lam) if lam is not None else None
         _check(lib().mfmg_smooth(self.handle, level, _dtype_code(x), n_vec, _ptr(x), _ptr(b), int(x_is_zero),
                                  lp, _stream()))
         return x
 
     def residual(self, level, r, b, x, n_vec=1):
+        n = self._n(level) * self._nv(n_vec)
+        _vecs((r, n, "r", None, None), (b, n, "b", None, r), (x, n, "x", None, r))
         _check(lib().mfmg_residual(self.handle, level, _dtype_code(r), n_vec, _ptr(r), _ptr(b), _ptr(x),
                                    _stream()))
         return r
 
     def prolongate_add(self, fine_level, dst_fine, src_coarse, n_vec=1):
+        nv = self._nv(n_vec)
+        _vecs((dst_fine, self._n(fine_level) * nv, "dst_fine", None, None),
+              (src_coarse, self._n(fine_level - 1) * nv, "src_coarse", None, dst_fine))
         _check(lib().mfmg_prolongate_add(self.handle, fine_level, _dtype_code(dst_fine), n_vec, _ptr(dst_fine),
                                          _ptr(src_coarse), _stream()))
         return dst_fine
 
     def restrict_add(self, fine_level, dst_coarse, src_fine, n_vec=1):
+        nv = self._nv(n_vec)
+        _vecs((dst_coarse, self._n(fine_level - 1) * nv, "dst_coarse", None, None),
+              (src_fine, self._n(fine_level) * nv, "src_fine", None, dst_coarse))
         _check(lib().mfmg_restrict_add(self.handle, fine_level, _dtype_code(dst_coarse), n_vec,
                                        _ptr(dst_coarse), _ptr(src_fine), _stream()))
         return dst_coarse
 
     def coarse_solve(self, x, b, n_vec=1):
+        n = self._n(0) * self._nv(n_vec)
+        _vecs((x, n, "x", None, None), (b, n, "b", None, x))
         _check(lib().mfmg_coarse_solve(self.handle, _dtype_code(x), n_vec, _ptr(x), _ptr(b), _stream()))
         return x
 
     def fmg(self, x, b, cycles=1, n_vec=1):
+        n = self._n(LEVEL_ACTIVE) * self._nv(n_vec)
+        _vecs((x, n, "x", _f64("x"), None), (b, n, "b", _f64("b"), None))
         _check(lib().mfmg_fmg(self.handle, n_vec, _ptr(x), _ptr(b), cycles, _stream()))
         return x
 
     def copy_to_mg(self, level, dst, src, n_vec=1):
+        nv = self._nv(n_vec)
+        _vecs((dst, self._n(level) * nv, "dst", None, None),
+              (src, self._n(LEVEL_ACTIVE) * nv, "src", _f64("src"), None))
         _check(lib().mfmg_copy_to_mg(self.handle, level, n_vec, _ptr(dst), _ptr(src), _stream()))
         return dst
 
     def copy_from_mg(self, level, dst, src, n_vec=1):
+        nv = self._nv(n_vec)
+        _vecs((dst, self._n(LEVEL_ACTIVE) * nv, "dst", _f64("dst"), None),
+              (src, self._n(level) * nv, "src", None, None))
         _check(lib().mfmg_copy_from_mg(self.handle, level, n_vec, _ptr(dst), _ptr(src), _stream()))
         return dst
 
     def vcycle(self, x, b, n_vec=1):
+        n = self._n(LEVEL_ACTIVE) * self._nv(n_vec)
+        _vecs((x, n, "x", _f64("x"), None), (b, n, "b", _f64("b"), None))
         _check(lib().mfmg_vcycle(self.handle, n_vec, _ptr(x), _ptr(b), _stream()))
         return x
 
     def solve(self, x, b, rtol=1e-10, max_it=100, flexible=False, n_vec=1, raise_on_fail=True):
+        n = self._n(LEVEL_ACTIVE) * self._nv(n_vec)
+        _vecs((x, n, "x", _f64("x"), None), (b, n, "b", _f64("b"), None))
         st = SolveStats()
         code = lib().mfmg_solve(self.handle, n_vec, _ptr(x), _ptr(b), rtol, max_it, int(flexible), C.byref(st),
                                 _stream())
@@ -332,11 +408,21 @@ class Solver:
 
     def rhs(self, b, kind=RHS_CONST, params=(1.0,), n_terms=0, n_vec=1, level=LEVEL_ACTIVE):
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+        nv = self._nv(n_vec)
+        need = {RHS_CONST: 1, RHS_SINE: 2}.get(kind, 5 * n_terms * nv)
+        if kind == RHS_GAUSS and n_terms < 1:
+            raise ValueError("n_terms must be >= 1 for Gaussian sums")
+        if p.size < need:
+            raise ValueError(f"params: {p.size} values, the load of kind {kind} reads {need}")
+        _vecs((b, self._n(level) * nv, "b", _f64("b"), None))
         _check(lib().mfmg_rhs(self.handle, level, kind, p.ctypes.data_as(C.POINTER(C.c_double)), n_terms, n_vec,
                               _ptr(b), _stream()))
         return b
 
     def distribute(self, x, out, level=LEVEL_ACTIVE):
+        info = self.level_info(level)
+        _vecs((x, info["n_dofs"], "x", _f64("x"), None),
+              (out, info["n_cells"] * (info["degree"] + 1) ** 3, "out", _f64("out"), None))
         _check(lib().mfmg_distribute(self.handle, level, _ptr(x), _ptr(out), _stream()))
         return out
 
@@ -372,6 +458,15 @@ class Solver:
         return t
 
     def net_loss_grad(self, X, T, grad):
+        import torch
+        n = self.net_n_params()
+        nq = (n - 4416) // 129  # n = (nq + 3) 64 + 64 + 64 64 + 64 + 64 nq + nq
+        nin = nq + 3
+        if X.dim() != 2 or X.shape[1] != nin:
+            raise ValueError(f"X: expected shape (rows, {nin}), got {tuple(X.shape)}")
+        _vecs((X, X.shape[0] * nin, "X", torch.float32, None),
+              (T, X.shape[0] * nq, "T", torch.float32, None),
+              (grad, n, "grad", torch.float32, None))
         loss = C.c_float()
         _check(lib().mfmg_net_loss_grad(self.handle, X.shape[0], _ptr(X), _ptr(T), _ptr(grad), C.byref(loss)))
         return loss.value
@@ -381,6 +476,14 @@ class Solver:
         hist = (C.c_float * epochs)()
         _check(lib().mfmg_net_train(self.handle, C.byref(d), hist))
         return list(hist)
+
+    def net_infer(self, y, b):
+        """y = the network's coarse correction of the level-0 right-hand side b
+        (no residual check); y and b of one dtype."""
+        n = self._n(0)
+        _vecs((b, n, "b", None, None), (y, n, "y", None, b))
+        _check(lib().mfmg_net_infer(self.handle, _dtype_code(b), _ptr(y), _ptr(b), _stream()))
+        return y
 
     def net_mode(self, mode, tau=0.5):
         _check(lib().mfmg_net_mode(self.handle, mode, tau))

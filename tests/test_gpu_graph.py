@@ -74,3 +74,36 @@ def test_other_coarse_modes_stay_eager():
     assert float((out[0][0] - out[1][0]).abs().max()) <= 1e-12 * float(out[0][0].abs().max())
     E.close()
     G.close()
+
+
+def test_graph_solves_with_changing_vector_count():
+    """One context with max_rhs = 8: a solve of one vector, then of 8
+    interleaved vectors that reuse the same work buffers, then one vector
+    again.  Each (x, b, n_vec) gets its own eager first cycle and its own
+    graph, and every graph solve equals the eager solve."""
+    from paper_2203_12292_amd import mfmg
+    mesh = mfmg.Mesh(DESCS["cfg1"])
+    print("[setup] cfg1 k=2 max_rhs=8 graph and eager", flush=True)
+    E = mfmg.Solver(mesh, 2, mfmg.SCHEME_H, max_rhs=8)
+    G = mfmg.Solver(mesh, 2, mfmg.SCHEME_H, max_rhs=8, graph_vcycle=True)
+    n = E.n_dofs()
+    for nv in (1, 8, 1, 8):
+        params = np.concatenate([synth.gaussian_rhs(500 + v, 2, 0.05, 0.3, "normal", 0.0, 1.0)
+                                 for v in range(nv)])
+        b = torch.zeros(n * nv, dtype=torch.float64, device=DEV)
+        E.rhs(b, mfmg.RHS_GAUSS, params, n_terms=2, n_vec=nv)
+        out = []
+        for S in (E, G):
+            for _ in range(2):  # the second solve of G replays its graphs
+                x = torch.zeros_like(b)
+                st = S.solve(x, b, rtol=1e-10, max_it=60, n_vec=nv)
+                torch.cuda.synchronize()
+            out.append((x, st))
+        scale = float(out[0][0].abs().max())
+        d = float((out[1][0] - out[0][0]).abs().max()) / scale
+        print(f"[graph nv={nv}] {out[0][1]['iterations']} / {out[1][1]['iterations']} it, graph vs eager {d:.1e}",
+              flush=True)
+        assert out[0][1]["converged"] and out[1][1]["iterations"] == out[0][1]["iterations"]
+        assert d <= 1e-12
+    E.close()
+    G.close()

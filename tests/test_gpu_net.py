@@ -128,3 +128,61 @@ def test_training_and_gain():
     # what the network gains over no coarse correction: its corrections
     # leave a clearly smaller coarse residual than 1
     assert np.mean(rels) < 0.8
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_net_infer_matches_oracle(dtype):
+    """mfmg_net_infer against the oracle's forward pass with node averaging
+    and the s-scaling, element by element on every coarse DoF (shared nodes
+    of 2, 4 and 8 cells; Dirichlet nodes enter as zero inputs), for fixed
+    random parameters.  FP32 network arithmetic: 1e-5 of the largest entry
+    (the input and output of a bfloat16 level are rounded to 8 bits: the
+    oracle gets the rounded input, the output is compared at 1e-2)."""
+    S = cfg1_solver()
+    H = oracle_hierarchy("cfg1", 2)
+    Sp = H.spaces[0]
+    P0 = perm_from_codes(Sp.codes_array(), S.dof_codes(0))
+    rng = np.random.default_rng(21)
+    theta = mlp.init_params(13) + 0.05 * rng.standard_normal(S.net_n_params())
+    S.net_set_params(theta.astype(np.float32))
+    theta32 = S.net_get_params().astype(np.float64)
+    for trial in range(3):
+        b = rng.standard_normal(Sp.n_dofs) * (10.0 ** (trial - 1))
+        g = np.zeros(len(P0))
+        g[P0] = b
+        bg = torch.tensor(g, dtype=dtype, device=DEV)
+        yg = torch.full_like(bg, float("nan"))
+        S.net_infer(yg, bg)
+        torch.cuda.synchronize()
+        b_used = bg.double().cpu().numpy()[P0]
+        want = mlp.coarse_correction(theta32, Sp, b_used)
+        got = yg.double().cpu().numpy()[P0]
+        err = np.abs(got - want).max() / np.abs(want).max()
+        print(f"[net infer {dtype}] trial {trial}: max error {err:.2e} of the largest entry", flush=True)
+        assert err < (1e-2 if dtype == torch.bfloat16 else 1e-5), (trial, err)
+    zero = torch.zeros(len(P0), dtype=dtype, device=DEV)
+    y0 = torch.ones_like(zero)
+    S.net_infer(y0, zero)
+    torch.cuda.synchronize()
+    assert float(y0.abs().max()) == 0.0
+
+
+def test_net_unsupported_above_degree_two():
+    """A Q3 coarse level (64 nodes per cell) has no network: the kernels hold
+    nq + 3 <= 64 values per row, so set-up leaves it out and every network
+    call reports MFMG_ERR_UNSUPPORTED, while the exact coarse solve works."""
+    from paper_2203_12292_amd import mfmg
+    print("[setup] tiny Q3 (coarse level 4^3 Q3, 1331 DoFs)", flush=True)
+    S = mfmg.Solver(mfmg.Mesh(synth.CFG1_TINY), 3)
+    assert S.n_dofs(0) <= 2048
+    with pytest.raises(mfmg.MfmgError) as e:
+        S.net_n_params()
+    assert e.value.code == mfmg.ERR_UNSUPPORTED
+    with pytest.raises(mfmg.MfmgError) as e:
+        S.net_mode(mfmg.COARSE_LEARNED)
+    assert e.value.code == mfmg.ERR_UNSUPPORTED
+    b = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
+    S.rhs(b)
+    x = torch.zeros_like(b)
+    assert S.solve(x, b, rtol=1e-10, max_it=40)["converged"]
+    S.close()

@@ -250,7 +250,7 @@ def test_distribute(name, k):
         assert np.abs(out[c] - distribute_values(Sp, cell, x)).max() < 1e-13
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_discretisation_convergence_on_gpu(k):
     """-Lap u = 3 pi^2 u, u = sin(pi x) sin(pi y) sin(pi z) on [0,1]^3: the
     L2 error of the GPU solution (solve to 1e-12, node values from the

@@ -64,6 +64,35 @@ def test_load_vector_integrates_polynomials():
     assert abs(b.sum() - 0.5 * (1.0 / 3.0)) < 1e-15
 
 
+# Lagrange polynomials on the Gauss-Lobatto nodes {0, 1} and {0, 1/2, 1},
+# written out by hand as coefficient lists in ascending powers of t
+_LAGRANGE = {1: [[1, -1], [0, 1]],                    # 1 - t, t
+             2: [[1, -3, 2], [0, 4, -4], [0, -1, 2]]}  # 2(t-1/2)(t-1), -4t(t-1), 2t(t-1/2)
+
+
+def _moment(p, coeffs):
+    """int_0^1 t^p l(t) dt in exact rational arithmetic."""
+    from fractions import Fraction
+    return sum(Fraction(c, p + i + 1) for i, c in enumerate(coeffs))
+
+
+@pytest.mark.parametrize("k,powers", [(1, (1, 2, 0)), (1, (0, 1, 2)), (2, (1, 2, 3)), (2, (3, 0, 2))])
+def test_load_vector_entries_closed_form(k, powers):
+    """Entry (a, b, c) of the load of f = x^px y^py z^pz is the product of the
+    1D moments int t^p l_a, int t^p l_b, int t^p l_c (Gauss with k+1 points is
+    exact for these degrees).  The powers differ per axis, so a swapped axis
+    or a node order other than x fastest fails."""
+    px, py, pz = powers
+    b = fe.reference_load(k, lambda p: p[:, 0] ** px * p[:, 1] ** py * p[:, 2] ** pz)
+    L = _LAGRANGE[k]
+    n = k + 1
+    for c in range(n):
+        for bb in range(n):
+            for a in range(n):
+                want = _moment(px, L[a]) * _moment(py, L[bb]) * _moment(pz, L[c])
+                assert abs(b[a + n * bb + n * n * c] - float(want)) < 1e-16, (a, bb, c)
+
+
 def test_basis_partition_of_unity_and_gradients():
     rng = np.random.default_rng(0)
     xi = rng.uniform(0, 1, size=(20, 3))

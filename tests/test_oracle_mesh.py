@@ -80,3 +80,36 @@ def test_workload_meshes_sizes():
     assert seq == [2808, 428, 113, 64]
     seq = [m.n_leaves() for m in octree.gc_sequence(octree.build_mesh(synth.CFG1_TINY))]
     assert seq == [386, 92, 64]
+
+
+def n_dofs_entities(tree, k):
+    """DoFs of a Q_k space counted per geometric entity of the leaves, as the
+    paper's p=4 column counts them: every vertex, edge, face and cell of every
+    leaf is one entity (a coarse face or edge next to finer leaves and the
+    finer leaves' own faces and edges are different entities), carrying 1,
+    k-1, (k-1)^2 and (k-1)^3 DoFs.  An entity is identified by its centre on
+    the doubled finest lattice and the axes along which it extends."""
+    top = tree.n_levels()
+    offs = np.array([(a, b, c) for c in range(3) for b in range(3) for a in range(3)], dtype=np.int64)
+    keys = {0: [], 1: [], 2: [], 3: []}
+    for l, cells in tree.all_leaves():
+        for off in offs:
+            v = (2 * cells + off[None, :]) << (top - l)
+            ext = off == 1
+            keys[int(ext.sum())].append(octree.pack(v[:, 0], v[:, 1], v[:, 2]) * 8
+                                        + int(ext[0]) + 2 * int(ext[1]) + 4 * int(ext[2]))
+    n = {d: np.unique(np.concatenate(v)).size for d, v in keys.items()}
+    assert n[3] == tree.n_leaves()
+    return n[0] + (k - 1) * n[1] + (k - 1) ** 2 * n[2] + (k - 1) ** 3 * n[3]
+
+
+@pytest.mark.parametrize("case", ["octant", "shell"])
+def test_dofs_p4(case):
+    """The p=4 DoF column of the paper's mesh table (two digits)."""
+    g = GOLD[case]
+    for i, L in enumerate(g["L"]):
+        desc = synth.octant_mesh(L) if case == "octant" else synth.shell_mesh(L)
+        t = octree.build_mesh(desc)
+        assert two_digits(n_dofs_entities(t, 4)) == g["dofs_p4_2digit"][i], (case, L)
+        # at p = 1 the entity count is the vertex count of the p=1 column
+        assert n_dofs_entities(t, 1) == octree.n_vertices(t)
