@@ -276,6 +276,60 @@ def cpu_baseline(desc, k, target_seconds=15.0, max_cells=4000):
     return dt, passes, len(local), n_cells_total
 
 
+PROFILE_WORKLOADS = {
+    # name: (mesh descriptor name in synth, degree, scheme, level dtype, vectors, what runs)
+    "q4_f64_vmult": ("CFG2", 4, "h_then_p", "f64", 1, "vmult"),
+    "q4_f32_vmult": ("CFG2", 4, "h_then_p", "f32", 1, "vmult"),
+    "q6_f32x8_vmult": ("CFG4", 6, "p_then_h", "f32", 8, "vmult"),
+    "q6_f32x8_transfer": ("CFG4", 6, "p_then_h", "f32", 8, "transfer"),
+    "q6_f32x8_smooth": ("CFG4", 6, "p_then_h", "f32", 8, "smooth"),
+    "q4_f64_smooth": ("CFG2", 4, "h_then_p", "f64", 1, "smooth"),
+}
+
+
+def run_profile_workload(name, steps, warmup):
+    """Set up one workload and run only its kernels `steps` times after
+    `warmup` untimed runs: the finest-level operator (vmult), the transfer
+    between the finest level and the next (prolongate_add + restrict_add), or
+    one Chebyshev smoothing step of degree 3 on the finest level (smooth).
+    Prints the mean HIP-event time per run (library stream)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2203_12292_amd import mfmg
+    mesh_name, k, scheme, dt, nv, what = PROFILE_WORKLOADS[name]
+    schemes = {"h": mfmg.SCHEME_H, "h_then_p": mfmg.SCHEME_H_THEN_P, "p_then_h": mfmg.SCHEME_P_THEN_H}
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt]
+    code = {"f64": mfmg.F64, "f32": mfmg.F32}[dt]
+    dev = torch.device("cuda:0")
+    print(f"[profile] {name}: set-up", file=sys.stderr, flush=True)
+    S = mfmg.Solver(mfmg.Mesh(getattr(synth, mesh_name)), k, schemes[scheme], level_dtypes=[code], max_rhs=nv)
+    fine = S.n_levels - 1
+    n = S.n_dofs(fine)
+    nc = S.n_dofs(fine - 1)
+    x = torch.from_numpy(synth.uniform_vector(n * nv, seed=12292)).to(dev).to(tdt)
+    y = torch.zeros_like(x)
+    xc = torch.from_numpy(synth.uniform_vector(nc * nv, seed=7)).to(dev).to(tdt)
+    yc = torch.zeros_like(xc)
+    if what == "vmult":
+        def run():
+            S.vmult(fine, y, x, n_vec=nv)
+    elif what == "transfer":
+        def run():
+            S.prolongate_add(fine, y, xc, n_vec=nv)
+            S.restrict_add(fine, yc, x, n_vec=nv)
+    else:
+        def run():
+            S.smooth(fine, y, x, x_is_zero=False, n_vec=nv)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ms = _events_time(run, steps, torch.cuda.current_stream())
+    print(f"[profile] {name}: {n} DoFs x {nv} vectors, {float(np.mean(ms)):.4f} ms per run", file=sys.stderr,
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +343,12 @@ def main():
     ap.add_argument("--pmc-command", action="append", default=[], help="command lines to quote in the summary")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="print the kernel-trace summary of a profiled run and exit (no GPU)")
+    ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
+                    help="run only the kernels of one workload --steps times (for rocprofv3) and exit")
     args = ap.parse_args()
+    if args.profile:
+        run_profile_workload(args.profile, args.steps, args.warmup)
+        return
     if args.trace_summary:
         print(trace_summary(args.trace_summary[0], args.trace_summary[1], args.pmc_command))
         return

@@ -1,5 +1,8 @@
 """Multigrid level hierarchies (oracle).
 
+``geometry`` (a descriptor of ``oracle.geometry``) maps the cells of every
+level by the same coarse-cell trilinear maps, so the levels stay nested.
+
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 Level sequences, coarse to fine, as (mesh, degree) pairs:
@@ -54,9 +57,11 @@ class Hierarchy:
     coarse solve then acts on a finer level, which may have hanging nodes
     (the early switch to the coarse-grid solver of the outlook, Section 8)."""
 
-    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0, coef=None):
+    def __init__(self, tree, k, scheme="h", cheb_degree=3, dirichlet=True, drop_coarse=0, coef=None,
+                 geometry=None):
         self.pairs = level_pairs(tree, k, scheme)[drop_coarse:]
-        self.spaces = [Space(m, d, dirichlet=dirichlet, coef=coef, coef_fine=tree) for m, d in self.pairs]
+        self.spaces = [Space(m, d, dirichlet=dirichlet, coef=coef, coef_fine=tree, geometry=geometry)
+                       for m, d in self.pairs]
         self.levels = []
         for l, S in enumerate(self.spaces):
             A = assemble_stiffness(S)

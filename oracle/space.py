@@ -108,8 +108,13 @@ class Space:
     -div(c grad u) with c constant per cell (``CellCoefficient`` over the
     finest mesh ``coef_fine``, by default ``tree`` itself)."""
 
-    def __init__(self, tree, k, dirichlet=True, build=True, coef=None, coef_fine=None):
+    def __init__(self, tree, k, dirichlet=True, build=True, coef=None, coef_fine=None, geometry=None):
         self.tree = tree
+        # mapped cells (``oracle.geometry``): a geometry descriptor, None for cubes
+        self.geometry = None
+        if geometry is not None and geometry["kind"] != 0:
+            from .geometry import CoarseTrilinearGeometry
+            self.geometry = CoarseTrilinearGeometry(tree, geometry)
         self.coef = CellCoefficient(coef, coef_fine if coef_fine is not None else tree) if coef is not None else None
         self.k = int(k)
         self.n = self.k + 1
@@ -256,6 +261,54 @@ class Space:
     def cell_coef(self, cell):
         return 1.0 if self.coef is None else self.coef(cell)
 
+    def element_matrix(self, cell):
+        """c_e times the cell's Laplace matrix: h A_ref on a cube of side h;
+        on a mapped cell, Gauss (k+1)^3 quadrature of
+        |det J| (J^{-T} grad phi_i) . (J^{-T} grad phi_j) with the Jacobian
+        J = dx/dxi of the cell map at every quadrature point."""
+        c = self.cell_coef(cell)
+        if self.geometry is None:
+            return (self.cell_h(cell) * c) * fe.reference_stiffness(self.k)
+        n = self.n
+        xq, wq = fe.gauss(n)
+        pts = np.array([(xq[a], xq[b], xq[d]) for d in range(n) for b in range(n) for a in range(n)])
+        w3 = np.array([wq[a] * wq[b] * wq[d] for d in range(n) for b in range(n) for a in range(n)])
+        G = fe.basis_gradient_at(self.k, pts)                 # (nq, n^3, 3) reference gradients
+        J = self.geometry.jacobians(cell, pts)               # (nq, 3, 3)
+        det = np.abs(np.linalg.det(J))
+        phys = np.linalg.solve(np.transpose(J, (0, 2, 1)), np.transpose(G, (0, 2, 1)))  # J^T g = grad_xi
+        return c * np.einsum("q,qdi,qdj->ij", w3 * det, phys, phys)
+
+    def element_load(self, cell, f):
+        """int_e f phi_i with Gauss (k+1)^3 points (|det J| weights on mapped cells)."""
+        l, i, j, m = cell
+        if self.geometry is None:
+            h = self.cell_h(cell)
+            corner = self.tree.lo + h * np.array([i, j, m], float)
+            return h ** 3 * fe.reference_load(self.k, lambda xi: f(corner[None, :] + h * xi))
+        n = self.n
+        xq, wq = fe.gauss(n)
+        pts = np.array([(xq[a], xq[b], xq[d]) for d in range(n) for b in range(n) for a in range(n)])
+        w3 = np.array([wq[a] * wq[b] * wq[d] for d in range(n) for b in range(n) for a in range(n)])
+        det = np.abs(np.linalg.det(self.geometry.jacobians(cell, pts)))
+        return fe.basis_at(self.k, pts).T @ (w3 * det * f(self.geometry.points(cell, pts)))
+
+    def physical_dof_points(self):
+        """Coordinates of the free DoFs after the cell map (the reference
+        lattice points for cubes)."""
+        if self.geometry is None:
+            return self.dof_points()
+        out = np.zeros((self.n_dofs, 3))
+        xi = self.xi
+        n = self.n
+        ref = np.array([(xi[a], xi[b], xi[c]) for c in range(n) for b in range(n) for a in range(n)])
+        for cell in self.cells:
+            pts = self.geometry.points(cell, ref)
+            for q, row in enumerate(self.cell_rows(cell)):
+                if len(row) == 1 and row[0][1] == 1.0:
+                    out[self.key_index[row[0][0]]] = pts[q]
+        return out
+
     def local_constraint_matrix(self, cell):
         """(global ids, dense C_e of shape (n^3, m))."""
         rows = self.cell_rows(cell)
@@ -294,14 +347,14 @@ class Space:
 
 # -- assembled operators -----------------------------------------------------------
 def assemble_stiffness(space):
-    """A = sum_e C_e^T (c_e h_e A_ref) C_e as scipy CSR (n_dofs x n_dofs)."""
-    Aref = fe.reference_stiffness(space.k)
+    """A = sum_e C_e^T A_e C_e as scipy CSR (n_dofs x n_dofs), A_e the
+    element matrix (c_e h_e A_ref on cubes)."""
     I, J, V = [], [], []
     for cell in space.cells:
         ids, C = space.local_constraint_matrix(cell)
         if ids.size == 0:
             continue
-        Al = C.T @ ((space.cell_h(cell) * space.cell_coef(cell)) * Aref) @ C
+        Al = C.T @ space.element_matrix(cell) @ C
         I.append(np.repeat(ids, ids.size))
         J.append(np.tile(ids, ids.size))
         V.append(Al.ravel())
@@ -320,11 +373,7 @@ def assemble_load(space, f):
         ids, C = space.local_constraint_matrix(cell)
         if ids.size == 0:
             continue
-        l, i, j, m = cell
-        h = space.cell_h(cell)
-        corner = space.tree.lo + h * np.array([i, j, m], float)
-        be = h ** 3 * fe.reference_load(space.k, lambda xi: f(corner[None, :] + h * xi))
-        b[ids] += C.T @ be
+        b[ids] += C.T @ space.element_load(cell, f)
     return b
 
 
@@ -413,9 +462,14 @@ def l2_error(space, x, u_exact, extra=3):
     err2 = 0.0
     for cell in space.cells:
         l, i, j, m = cell
-        h = space.cell_h(cell)
-        corner = space.tree.lo + h * np.array([i, j, m], float)
         uh = Phi @ distribute_values(space, cell, x)
-        ue = u_exact(corner[None, :] + h * pts)
-        err2 += h ** 3 * np.sum(w3 * (uh - ue) ** 2)
+        if space.geometry is None:
+            h = space.cell_h(cell)
+            corner = space.tree.lo + h * np.array([i, j, m], float)
+            ue = u_exact(corner[None, :] + h * pts)
+            err2 += h ** 3 * np.sum(w3 * (uh - ue) ** 2)
+        else:
+            ue = u_exact(space.geometry.points(cell, pts))
+            det = np.abs(np.linalg.det(space.geometry.jacobians(cell, pts)))
+            err2 += np.sum(w3 * det * (uh - ue) ** 2)
     return np.sqrt(err2)

@@ -6,6 +6,11 @@ FP64 result for the same (rounded) inputs, relative to the largest entry.
 The measured errors are printed per result; the bounds are those of the
 operator tests: FP32 2e-5, bfloat16 2e-2 (8 significant bits; the Chebyshev
 smoother stores x and d in the level type after each of its 3 steps, 3e-2).
+The transfers add into a vector of the level type: a DoF receives one
+addition per transfer group it belongs to (at most 8) and each rounds to the
+storage type, so their bound is (1 + 8) u (max|base| + max|P x|) / max|P x|
+with the unit roundoff u of the type (2^-8 for bfloat16), or the FP32
+operator bound if larger.
 """
 import functools
 
@@ -60,6 +65,10 @@ def test_level_ops_against_fp64_oracle(name, k, dtype):
     rng = np.random.default_rng(17)
     tol = TOL[dtype]
     worst = {}
+    u = {torch.float32: 2.0 ** -24, torch.bfloat16: 2.0 ** -8}[dtype]
+
+    def add_bound(base, ref):
+        return max(tol, 9 * u * (np.abs(base).max() + np.abs(ref).max()) / np.abs(ref).max())
 
     def report(op, l, e, bound):
         print(f"[{dtype} err] {name} Q{k} level {l} {op}: {e:.2e} (bound {bound:.0e})", flush=True)
@@ -104,10 +113,12 @@ def test_level_ops_against_fp64_oracle(name, k, dtype):
         xc = put(rng.uniform(-1, 1, Pm.shape[1]), P[l - 1], dtype)
         S.prolongate_add(l, base, xc)
         torch.cuda.synchronize()
-        report("prolongate_add", l, err(get(base, P[l]) - base_used, Pm @ get(xc, P[l - 1])), tol)
+        ref = Pm @ get(xc, P[l - 1])
+        report("prolongate_add", l, err(get(base, P[l]) - base_used, ref), add_bound(base_used, ref))
         basec = put(rng.uniform(-1, 1, Pm.shape[1]), P[l - 1], dtype)
         basec_used = get(basec, P[l - 1])
         S.restrict_add(l, basec, xg)
         torch.cuda.synchronize()
-        report("restrict_add", l, err(get(basec, P[l - 1]) - basec_used, Pm.T @ x), tol)
+        ref = Pm.T @ x
+        report("restrict_add", l, err(get(basec, P[l - 1]) - basec_used, ref), add_bound(basec_used, ref))
     print(f"[{dtype} worst] {name} Q{k}: " + ", ".join(f"{op} {e:.1e}" for op, e in worst.items()), flush=True)
