@@ -237,6 +237,21 @@ int mfmg_host_ls_level(mfmg_mesh mesh, int level, int degree, int64_t* n_dofs, i
 int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src,
                void* stream);
 
+/* [async] dst = A^(l) src as mfmg_vmult (same kernels, same result), for
+ * callers that cannot allocate memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Allocates nothing: the
+ * operator's work space (the partial sums of the DoFs shared between cell
+ * batches, and for MFMG_BF16 the FP32 result before rounding) lives in one
+ * fixed device array of 64 MiB per GPU, held by the library until the
+ * process ends.  A level whose work space exceeds it
+ * (sizeof(arithmetic type) x n_vec x shared entries, + 4 x n_vec x n_dofs
+ * for MFMG_BF16) is refused with MFMG_ERR_UNSUPPORTED before any work.  All
+ * calls on one GPU share that array: two calls that overlap in time on one
+ * GPU (different streams, or threads) race and give wrong results; calls
+ * ordered on one stream are safe. */
+int mfmg_vmult_noalloc(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src,
+                       void* stream);
+
 /* [async] diag = diagonal of A^(l) (Eq. impl:mf:diagonal, unit-vector
  * applications per cell with C_e applied from both sides). */
 int mfmg_diagonal(mfmg_ctx ctx, int level, int dtype, void* diag, void* stream);

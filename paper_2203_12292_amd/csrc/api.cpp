@@ -1,7 +1,9 @@
 // extern "C" entry points (include/mfmg.h).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "context.hpp"
 #include "fe1d.hpp"
@@ -11,8 +13,33 @@ struct mfmg_ctx_s {
   mfmg::Context ctx;
 };
 
+// Work space of mfmg_vmult_noalloc: one file-scope device array per GPU the
+// library runs on (it lives until the process ends).  Host code never passes
+// the array's name to a kernel: it looks up the array's device address once
+// per device and uses that.
+#define MFMG_NOALLOC_SCRATCH_BYTES (64ll << 20)
+static __device__ __align__(256) char scratch[MFMG_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 thread_local std::string g_last_error;
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device.
+void* scratch_device_ptr() {
+  static std::mutex mu;
+  static std::vector<void*> ptrs;
+  int dev = 0;
+  MFMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(ptrs.size()) <= dev) ptrs.resize(dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    MFMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MFMG_REQUIRE(p != nullptr, MFMG_ERR_HIP, "no device address for the scratch array");
+    ptrs[dev] = p;
+  }
+  return ptrs[dev];
+}
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -232,6 +259,38 @@ int mfmg_vmult(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const v
       mfmg::launch_acc_to_storage(dtype, L.n_dofs * n_vec, L.t.ptr, dst, as_stream(stream));
     } else {
       mfmg::launch_vmult(L.view, dtype, n_vec, dst, src, as_stream(stream));
+    }
+    return MFMG_OK;
+  });
+}
+
+int mfmg_vmult_noalloc(mfmg_ctx ctx, int level, int dtype, int n_vec, void* dst, const void* src, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_dtype(dtype);
+    check_nv(ctx->ctx, n_vec);
+    mfmg::Level& L = ctx->ctx.level(level);
+    check_vec(dst, L.n_dofs, "dst");
+    check_vec(src, L.n_dofs, "src");
+    if (L.n_dofs == 0) return MFMG_OK;
+    MFMG_REQUIRE(dst != src, MFMG_ERR_INVALID_ARG, "dst and src must not alias");
+    // scratch layout: the partial sums of the shared DoFs (arithmetic type),
+    // then for bfloat16 the FP32 result before its rounding to the storage type
+    const int64_t acc_bytes = dtype == MFMG_F64 ? 8 : 4;
+    const int64_t part = (static_cast<int64_t>(L.sh_idx.n) * n_vec * acc_bytes + 255) / 256 * 256;
+    const int64_t need = part + (dtype == MFMG_BF16 ? L.n_dofs * n_vec * 4 : 0);
+    MFMG_REQUIRE(need <= MFMG_NOALLOC_SCRATCH_BYTES, MFMG_ERR_UNSUPPORTED,
+                 "mfmg_vmult_noalloc: this level needs " + std::to_string(need) +
+                     " bytes of work space, more than the " + std::to_string(MFMG_NOALLOC_SCRATCH_BYTES) +
+                     " the library holds per GPU (use mfmg_vmult)");
+    char* ws = static_cast<char*>(scratch_device_ptr());
+    mfmg::CellView view = L.view;
+    view.partial = ws;
+    if (dtype == MFMG_BF16) {
+      mfmg::launch_vmult(view, dtype, n_vec, ws + part, src, as_stream(stream));
+      mfmg::launch_acc_to_storage(dtype, L.n_dofs * n_vec, ws + part, dst, as_stream(stream));
+    } else {
+      mfmg::launch_vmult(view, dtype, n_vec, dst, src, as_stream(stream));
     }
     return MFMG_OK;
   });

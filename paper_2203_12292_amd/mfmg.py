@@ -76,6 +76,7 @@ _SIGS = {
     "mfmg_level_dof_codes": (_I, [_P, _I, _I64P]),
     "mfmg_smoother_range": (_I, [_P, _I, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mfmg_vmult": (_I, [_P, _I, _I, _I, _P, _P, _P]),
+    "mfmg_vmult_noalloc": (_I, [_P, _I, _I, _I, _P, _P, _P]),
     "mfmg_diagonal": (_I, [_P, _I, _I, _P, _P]),
     "mfmg_smooth": (_I, [_P, _I, _I, _I, _P, _P, _I, C.POINTER(C.c_double), _P]),
     "mfmg_residual": (_I, [_P, _I, _I, _I, _P, _P, _P, _P]),
@@ -322,6 +323,14 @@ class Solver:
         n = self._n(level) * self._nv(n_vec)
         _vecs((src, n, "src", None, None), (dst, n, "dst", None, src))
         _check(lib().mfmg_vmult(self.handle, level, _dtype_code(src), n_vec, _ptr(dst), _ptr(src), _stream()))
+        return dst
+
+    def vmult_noalloc(self, level, dst, src, n_vec=1):
+        """dst = A src through the allocation-free entry point (fixed work space)."""
+        n = self._n(level) * self._nv(n_vec)
+        _vecs((src, n, "src", None, None), (dst, n, "dst", None, src))
+        _check(lib().mfmg_vmult_noalloc(self.handle, level, _dtype_code(src), n_vec, _ptr(dst), _ptr(src),
+                                        _stream()))
         return dst
 
     def diagonal(self, level, diag):
