@@ -233,10 +233,51 @@ def _events_time(fn, k, stream):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
-def cpu_baseline(desc, k, target_seconds=15.0, max_cells=4000):
+def _ebe_passes(local, x, seconds):
+    """Passes of the oracle's element-by-element apply over `local` in `seconds`
+    (one thread)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        passes = 0
+        while True:
+            for (C, Ae, _), xl in zip(local, x):
+                _ = C.T @ (Ae @ (C @ xl))
+            passes += 1
+            if time.time() - t0 >= seconds:
+                break
+        return passes, time.time() - t0
+
+
+_EBE = {}
+
+
+def _ebe_worker(args):
+    lo, hi, seconds = args
+    local, x = _EBE["local"], _EBE["x"]
+    passes, dt = _ebe_passes(local[lo:hi], x[lo:hi], seconds)
+    return passes * (hi - lo), dt
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(desc, k, target_seconds=10.0, max_cells=4000):
     """The oracle's element-by-element operator (sum_e C_e^T A_e C_e x) timed
     on a bounded sample of the workload's cells (set-up of the constraint rows
-    excluded, as the GPU set-up is)."""
+    excluded, as the GPU set-up is): on one core, and on every core of the
+    host (the sample split over one process per core, all timed at once).
+    Returns cells/s for both, the core counts and the sample size."""
+    import multiprocessing as mp
+
     import numpy as np
 
     from oracle import fe, octree
@@ -262,18 +303,39 @@ def cpu_baseline(desc, k, target_seconds=15.0, max_cells=4000):
         if time.time() - t_setup > 60:
             break
     x = [np.random.default_rng(i).uniform(-1, 1, m) for i, (_, _, m) in enumerate(local)]
+    passes, dt = _ebe_passes(local, x, target_seconds)
+    one = passes * len(local) / dt
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    _EBE["local"], _EBE["x"] = local, x
+    m = len(local)
+    chunks = [(m * w // cores, m * (w + 1) // cores, target_seconds) for w in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_ebe_worker, chunks)
+    _EBE.clear()
+    allc = sum(cells / dt for cells, dt in res)
+    return {"cells_per_s_1core": one, "cells_per_s_all": allc, "cores": cores, "n_sample": m,
+            "n_cells_total": n_cells_total, "seconds": target_seconds}
+
+
+def oracle_solve_baseline(desc, k):
+    """The oracle's own solver on a small workload: PCG (FP64) preconditioned
+    by its V-cycle (Chebyshev degree 3, exact coarse solve), x0 = 0, relative
+    residual 1e-10, f = 1; the hierarchy's assembly is excluded (as the GPU
+    set-up is).  One thread."""
     from threadpoolctl import threadpool_limits
+
+    from oracle import octree
+    from oracle.hierarchy import Hierarchy
+    from oracle.space import assemble_load, constant
+    t0 = time.time()
+    H = Hierarchy(octree.build_mesh(desc), k)
+    b = assemble_load(H.spaces[-1], constant(1.0))
+    setup = time.time() - t0
     with threadpool_limits(limits=1):
         t0 = time.time()
-        passes = 0
-        while True:
-            for (C, Ae, _), xl in zip(local, x):
-                _ = C.T @ (Ae @ (C @ xl))
-            passes += 1
-            if time.time() - t0 >= target_seconds:
-                break
+        x, its, hist = H.solve(b, rtol=1e-10)
         dt = time.time() - t0
-    return dt, passes, len(local), n_cells_total
+    return {"seconds": dt, "iterations": its, "free_dofs": int(b.size), "setup_s": round(setup, 1), "cores": 1}
 
 
 PROFILE_WORKLOADS = {
@@ -328,6 +390,44 @@ def run_profile_workload(name, steps, warmup):
     ms = _events_time(run, steps, torch.cuda.current_stream())
     print(f"[profile] {name}: {n} DoFs x {nv} vectors, {float(np.mean(ms)):.4f} ms per run", file=sys.stderr,
           flush=True)
+
+
+def hanging_node_overhead(k=4, reps=20):
+    """The operator on the paper's two test meshes, whose leaves carry
+    hanging-node constraints in very different shares (octant L = 7: 6 %,
+    shell L = 8: 38 %; Section 4), against a uniform mesh of similar size
+    without any: time per DoF and per application, FP64, and the extra time
+    per DoF relative to the uniform mesh (the paper's bound for high degrees
+    is 20 %, Section 3.2)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2203_12292_amd import mfmg
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, desc in (("uniform64", synth.mesh_desc("uniform64", 64, -1.0, 1.0, 0, [])),
+                       ("octant7", synth.octant_mesh(7)), ("shell8", synth.shell_mesh(8))):
+        print(f"[bench] hanging-node overhead: {name}", file=sys.stderr, flush=True)
+        mesh = mfmg.Mesh(desc)
+        cells, nh = mesh.info()
+        S = mfmg.Solver(mesh, k, mfmg.SCHEME_H, max_rhs=1)
+        fine = S.n_levels - 1
+        n = S.n_dofs(fine)
+        x = torch.from_numpy(synth.uniform_vector(n, seed=12292)).to(dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            S.vmult(fine, y, x)
+        ms = float(np.mean(_events_time(lambda: S.vmult(fine, y, x), reps, torch.cuda.current_stream())))
+        out[name] = {"cells": cells[-1], "hanging_cells": nh, "hanging_share": nh / cells[-1], "free_dofs": n,
+                     "ms": ms, "ns_per_dof": ms * 1e6 / n, "dofs_per_s": n / (ms * 1e-3),
+                     "hbm_frac": 16.0 * n / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+        del S, x, y
+        torch.cuda.empty_cache()
+    base = out["uniform64"]["ns_per_dof"]
+    for name in ("octant7", "shell8"):
+        out[name]["overhead_vs_uniform"] = out[name]["ns_per_dof"] / base - 1.0
+    return out
 
 
 def main():
@@ -612,16 +712,21 @@ def main():
             "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}
         del s4
         out["time_to_solve"] = dict(solves)
+        out["hanging_node_overhead_q4"] = hanging_node_overhead()
 
     if not args.skip_cpu_baseline:
-        dt, passes, n_sample, n_total = cpu_baseline(desc, k)
+        print("[bench] CPU baseline: the oracle on the host cores", file=sys.stderr, flush=True)
+        cb = cpu_baseline(desc, k)
         dofs_per_cell = n / cells[-1]
-        v = passes * n_sample * dofs_per_cell / dt
-        out["cpu_baseline"] = {"value": v, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
-                               "sample": f"element-by-element C_e^T A_e C_e apply (numpy FP64, one thread) "
-                                         f"over {n_sample} random cells of the {n_total}-cell mesh, {passes} "
-                                         f"passes in {dt:.1f} s; DoFs/s = cells/s x {dofs_per_cell:.1f} "
-                                         f"free DoFs per cell"}
+        out["cpu_baseline"] = {
+            "value": cb["cells_per_s_all"] * dofs_per_cell, "unit": "DoFs/s", "cores": cb["cores"],
+            "kind": "oracle",
+            "sample": f"element-by-element C_e^T A_e C_e apply (numpy FP64) over {cb['n_sample']} random cells of "
+                      f"the {cb['n_cells_total']}-cell mesh, {cb['seconds']:.0f} s per run, one process per core; "
+                      f"DoFs/s = cells/s x {dofs_per_cell:.1f} free DoFs per cell",
+            "value_1core": cb["cells_per_s_1core"] * dofs_per_cell,
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "oracle_solve_cube4_q2": oracle_solve_baseline(synth.CFG1, 2)}
     print(json.dumps(out), flush=True)
 
 

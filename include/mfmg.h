@@ -158,6 +158,28 @@ typedef struct {
                             (mfmg_fmg, one V-cycle per level) instead of
                             x0 = 0; the stopping rule stays relative to
                             ||b||.  Global-coarsening schemes only. */
+  int geom_kind;         /* cell geometry (Section 3.2: the quadrature-point
+                            operation with the Jacobian J = dx/dxi of each
+                            cell map).  The vertices of the coarse grid are
+                            moved; each coarse cell becomes the trilinear
+                            image of the cube through its moved vertices and
+                            its descendants inherit that map, so the levels
+                            stay nested.  With p = geom_params:
+                            0: none (axis-aligned cubes, the Kronecker form
+                               of the cell operator);
+                            1: affine, x' = M x with
+                               M = [[p0,p1,p2],[0,p3,p4],[0,0,p5]];
+                            2: interior bump, x' = x + p0 s(x) (p1,p2,p3),
+                               s(x) = prod_d sin(pi (x_d - lo)/(hi - lo))
+                               (the domain boundary stays in place).
+                            Kinds 1-2 use the general operator (values and
+                            reference gradients at the Gauss points, the
+                            metric term w |det J| J^-1 J^-T computed per
+                            point from 24 numbers per coarse cell), and the
+                            load vector integrates over the mapped cells.
+                            Global-coarsening schemes only; every cell map
+                            must keep det J > 0. */
+  double geom_params[8];
 } mfmg_level_desc;
 
 typedef struct {

@@ -59,6 +59,7 @@ class LevelSpace(Space):
     def __init__(self, tree, level, k, coef=None):
         self.tree = tree
         self.coef = CellCoefficient(coef, tree) if coef is not None else None
+        self.geometry = None  # local-smoothing levels are built on cubes
         self.level = int(level)
         self.k = int(k)
         self.n = self.k + 1

@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "dofs.hpp"
+#include "geometry.hpp"
 #include "kernels.hpp"
 #include "octree.hpp"
 
@@ -95,6 +96,11 @@ struct Context {
   mfmg_level_desc desc{};
   GraphCache graphs;
   CoefDesc coef;  // diffusion coefficient (constant per cell)
+  GeoDesc geo;    // cell geometry; kind 0: axis-aligned cubes
+  std::vector<double> geo_host;            // coarse-cell map coefficients [n0^3][24]
+  DeviceArray<double> geo64;
+  DeviceArray<float> geo32;
+  int geo_n0 = 0;
   std::vector<Octree> meshes;
   std::vector<Level> levels;  // 0 = coarsest
   // local smoothing: `levels` are the refinement levels and `active` is the

@@ -1,5 +1,6 @@
 // DoF numbering, gather maps, transfer categories (host side).
 #include "dofs.hpp"
+#include "geometry.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -596,7 +597,49 @@ void apply_constraints_host(std::vector<double>& u, uint32_t m, const Tables1D& 
 }
 }  // namespace
 
-std::vector<double> assemble_dense(const LevelDofs& L, const Tables1D& t) {
+// Element matrix of a mapped cell: Gauss (k+1)^3 quadrature of
+// c_e (w |det J| J^{-1} J^{-T}) grad_xi phi_i . grad_xi phi_j.
+static void mapped_element_matrix(const Cell& cell, uint32_t m, const Tables1D& t, const std::vector<double>& geo,
+                                  int n0, std::vector<double>& Ae) {
+  const int n = t.n, n3 = n * n * n;
+  std::vector<double> V(n * n), Dv(n * n);  // GLL basis and derivative at the Gauss points
+  for (int q = 0; q < n; ++q)
+    for (int i = 0; i < n; ++i) {
+      V[q * n + i] = lagrange(t.nodes, i, t.qp[q]);
+      Dv[q * n + i] = lagrange_deriv(t.nodes, i, t.qp[q]);
+    }
+  const int l = cell.level;
+  const int64_t I = cell.i >> l, J = cell.j >> l, K = cell.k >> l;
+  const double* A = &geo[(I + n0 * (J + static_cast<int64_t>(n0) * K)) * 24];
+  const double sc = std::ldexp(1.0, -l), coef = static_cast<double>(mask_coef(m));
+  std::fill(Ae.begin(), Ae.end(), 0.0);
+  std::vector<double> g(static_cast<size_t>(n3) * 3);
+  for (int qc = 0; qc < n; ++qc)
+    for (int qb = 0; qb < n; ++qb)
+      for (int qa = 0; qa < n; ++qa) {
+        double Jm[3][3], G[6];
+        geo_jacobian<double>(A, (cell.i - (I << l) + t.qp[qa]) * sc, (cell.j - (J << l) + t.qp[qb]) * sc,
+                             (cell.k - (K << l) + t.qp[qc]) * sc, Jm);
+        for (int d = 0; d < 3; ++d)
+          for (int e = 0; e < 3; ++e) Jm[d][e] *= sc;
+        geo_metric<double>(Jm, coef * t.qw[qa] * t.qw[qb] * t.qw[qc], G);
+        const double Gf[3][3] = {{G[0], G[1], G[2]}, {G[1], G[3], G[4]}, {G[2], G[4], G[5]}};
+        for (int i = 0; i < n3; ++i) {
+          const int a = i % n, b = (i / n) % n, c = i / (n * n);
+          g[3 * i + 0] = Dv[qa * n + a] * V[qb * n + b] * V[qc * n + c];
+          g[3 * i + 1] = V[qa * n + a] * Dv[qb * n + b] * V[qc * n + c];
+          g[3 * i + 2] = V[qa * n + a] * V[qb * n + b] * Dv[qc * n + c];
+        }
+        for (int i = 0; i < n3; ++i) {
+          double Gg[3];
+          for (int d = 0; d < 3; ++d) Gg[d] = Gf[d][0] * g[3 * i] + Gf[d][1] * g[3 * i + 1] + Gf[d][2] * g[3 * i + 2];
+          for (int j = 0; j < n3; ++j)
+            Ae[i * n3 + j] += Gg[0] * g[3 * j] + Gg[1] * g[3 * j + 1] + Gg[2] * g[3 * j + 2];
+        }
+      }
+}
+
+std::vector<double> assemble_dense(const LevelDofs& L, const Tables1D& t, const std::vector<double>* geo, int geo_n0) {
   const int n = t.n, k = t.k, n3 = n * n * n;
   const int64_t N = L.n_dofs;
   std::vector<double> A(static_cast<size_t>(N * N), 0.0);
@@ -606,14 +649,18 @@ std::vector<double> assemble_dense(const LevelDofs& L, const Tables1D& t) {
   for (int64_t c = 0; c < L.n_cells; ++c) {
     const uint32_t m = L.mask[c];
     const double h = L.h0 * std::ldexp(1.0, -mask_level(m)) * static_cast<double>(mask_coef(m));
-    for (int i = 0; i < n3; ++i)
-      for (int j = 0; j < n3; ++j) {
-        int a = i % n, b = (i / n) % n, cc = i / (n * n);
-        int a2 = j % n, b2 = (j / n) % n, c2 = j / (n * n);
-        Ae[i * n3 + j] = h * (t.K[a * n + a2] * t.M[b * n + b2] * t.M[cc * n + c2] +
-                              t.M[a * n + a2] * t.K[b * n + b2] * t.M[cc * n + c2] +
-                              t.M[a * n + a2] * t.M[b * n + b2] * t.K[cc * n + c2]);
-      }
+    if (geo) {
+      mapped_element_matrix(L.cells[c], m, t, *geo, geo_n0, Ae);
+    } else {
+      for (int i = 0; i < n3; ++i)
+        for (int j = 0; j < n3; ++j) {
+          int a = i % n, b = (i / n) % n, cc = i / (n * n);
+          int a2 = j % n, b2 = (j / n) % n, c2 = j / (n * n);
+          Ae[i * n3 + j] = h * (t.K[a * n + a2] * t.M[b * n + b2] * t.M[cc * n + c2] +
+                                t.M[a * n + a2] * t.K[b * n + b2] * t.M[cc * n + c2] +
+                                t.M[a * n + a2] * t.M[b * n + b2] * t.K[cc * n + c2]);
+        }
+    }
     // C (columns = constraint interpolation of unit slot vectors)
     for (int j = 0; j < n3; ++j) {
       std::fill(col.begin(), col.end(), 0.0);

@@ -145,7 +145,10 @@ struct EntityIndex {
 void ls_copy_pairs(const LevelDofs& level, const LevelDofs& active, const EntityIndex& index,
                    std::vector<int32_t>& level_dofs, std::vector<int32_t>& active_dofs);
 
-// Dense assembled matrix of a (small) level: sum_e C_e^T A_e C_e.
-std::vector<double> assemble_dense(const LevelDofs& L, const struct Tables1D& t);
+// Dense assembled matrix of a (small) level: sum_e C_e^T A_e C_e; with
+// `geo` (coarse-cell map coefficients, geometry.hpp; n0 coarse cells per
+// axis) the element matrices of the mapped cells, by quadrature.
+std::vector<double> assemble_dense(const LevelDofs& L, const struct Tables1D& t,
+                                   const std::vector<double>* geo = nullptr, int geo_n0 = 0);
 
 }  // namespace mfmg

@@ -18,6 +18,7 @@
 // operator, transposed z, x, y after it, then the scatter.
 #include "common.hpp"
 #include "fe1d.hpp"
+#include "geometry.hpp"
 #include "kernels.hpp"
 #include "slots.hpp"
 
@@ -408,7 +409,7 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 // the interpolation matrices of both halves.  Must be called by all lanes of
 // the wavefront.
 template <int K, typename T, typename Sync>
-__device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, T* __restrict__ B1, uint32_t m,
+__device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, uint32_t m,
                                                      int any_hang, T h, const OpTab2<T, K + 1>& tab,
                                                      const T* __restrict__ Hg, int ta, int tb, T (&u)[K + 1]) {
   constexpr int N = K + 1, N2 = N * N;
@@ -438,44 +439,48 @@ __device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, T* __re
 #pragma unroll
     for (int c = 0; c < N; ++c) u[c] = B0[c * N2 + tb * N + ta];  // own z-line, rewritten below
   }
-  T a[N], b[N];
+  // One n^3 buffer per cell carries the four transposes one after the
+  // other: a (z-lines -> y-lines), b (z -> y), c (y -> x), f (y -> x).  The
+  // lanes of a cell are one wavefront, whose LDS operations execute in
+  // order, so a buffer may be rewritten as soon as the previous read of it
+  // has been issued; Sync keeps the compiler from reordering across.
+  // Ordered to keep few values live: a dies into c and f once read back
+  // along y, then b adds M_y b to f, and so on.
+  T a[N], b[N], c[N], f[N];
   sym_mv<N>(tab.M, u, a);
   sym_mv<N>(tab.K, u, b);
 #pragma unroll
-  for (int c = 0; c < N; ++c) {
-    B0[c * N2 + tb * N + ta] = a[c];
-    B1[c * N2 + tb * N + ta] = b[c];
-  }
+  for (int q = 0; q < N; ++q) B0[q * N2 + tb * N + ta] = a[q];
   sync();
-  {
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      a[r] = B0[tb * N2 + r * N + ta];
-      b[r] = B1[tb * N2 + r * N + ta];
-    }
-    T c1[N], f1[N], f2[N];
-    sym_mv<N>(tab.M, a, c1);
-    sym_mv<N>(tab.K, a, f1);
-    sym_mv<N>(tab.M, b, f2);
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      B0[tb * N2 + r * N + ta] = c1[r];
-      B1[tb * N2 + r * N + ta] = f1[r] + f2[r];
-    }
-  }
+  for (int r = 0; r < N; ++r) a[r] = B0[tb * N2 + r * N + ta];
+  sym_mv<N>(tab.M, a, c);
+  sym_mv<N>(tab.K, a, f);
   sync();
-  {
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      a[r] = B0[tb * N2 + ta * N + r];
-      b[r] = B1[tb * N2 + ta * N + r];
-    }
-    T g1[N], g2[N];
-    sym_mv<N>(tab.K, a, g1);
-    sym_mv<N>(tab.M, b, g2);
+  for (int q = 0; q < N; ++q) B0[q * N2 + tb * N + ta] = b[q];
+  sync();
 #pragma unroll
-    for (int r = 0; r < N; ++r) u[r] = h * (g1[r] + g2[r]);
-  }
+  for (int r = 0; r < N; ++r) a[r] = B0[tb * N2 + r * N + ta];
+  sym_mv<N>(tab.M, a, b);
+#pragma unroll
+  for (int r = 0; r < N; ++r) f[r] += b[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = c[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) a[r] = B0[tb * N2 + ta * N + r];
+  sym_mv<N>(tab.K, a, c);
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = f[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) a[r] = B0[tb * N2 + ta * N + r];
+  sym_mv<N>(tab.M, a, b);
+#pragma unroll
+  for (int r = 0; r < N; ++r) u[r] = h * (c[r] + b[r]);
   if (!any_hang) return false;
   if (hang && hanging_line(m, 0, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 0), u);
 #pragma unroll
@@ -531,6 +536,243 @@ constexpr LaneLineTable<K> make_lane_lines() {
 template <int K>
 __constant__ LaneLineTable<K> kLaneLines = make_lane_lines<K>();
 
+// Gauss-point tables of the operator on mapped cells: S[q][i] = l_i(g_q)
+// (Gauss-Lobatto basis at the Gauss points), D[q][p] = L_p'(g_q) (derivative
+// of the Lagrange basis on the Gauss points: gradients from point values),
+// the Gauss points g and weights w on [0, 1].
+template <typename T, int N>
+struct MapTab {
+  T S[N * N];
+  T D[N * N];
+  T g[N];
+  T w[N];
+};
+
+template <typename T, int N>
+MapTab<T, N> make_maptab() {
+  const Tables1D& t = tables(N - 1);
+  MapTab<T, N> m;
+  for (int q = 0; q < N; ++q) {
+    m.g[q] = static_cast<T>(t.qp[q]);
+    m.w[q] = static_cast<T>(t.qw[q]);
+    for (int i = 0; i < N; ++i) {
+      m.S[q * N + i] = static_cast<T>(t.S[q * N + i]);
+      m.D[q * N + i] = static_cast<T>(lagrange_deriv(t.qp, i, t.qp[q]));
+    }
+  }
+  return m;
+}
+
+// y = A x (TRANS: y = A^T x) for an n x n table A
+template <int N, typename T, bool TRANS>
+__device__ __forceinline__ void mat_mv(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = (TRANS ? A[i] : A[i * N]) * x[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) acc += (TRANS ? A[j * N + i] : A[i * N + j]) * x[j];
+    y[i] = acc;
+  }
+}
+
+// Geometry of one cell of a mapped level: the coarse cell's map coefficients
+// (monomial form, see geometry.hpp) and the cell's box inside it,
+// t = (r + xi) * scale.
+template <typename T>
+struct CellGeo {
+  const T* A;
+  T r[3];
+  T scale;
+};
+
+// The cell pipeline C^T S^T Q S C on a mapped cell (Eq. impl:mf with the
+// general Q_e): values at the Gauss points by three sweeps of S, reference
+// gradients at the points by sweeps of D, the metric term
+// c_e w_q |det J| J^{-1} J^{-T} at every point (J from the cell's trilinear
+// map), the transposed sweeps D^T and S^T.  The one n^3 buffer B of the cell
+// re-distributes the values between the line directions.  Input: this lane's
+// z-line (x = ta, y = tb) of gathered slot values; output: the same z-line
+// of the result (the gather layout).  Hanging lines are interpolated as in
+// the axis-aligned pipeline (before: z in registers, y and x in LDS; after:
+// the transposes, z in registers, y and x in LDS).  Must be called by all
+// lanes of the wavefront.
+template <int K, typename T, typename Sync>
+__device__ __forceinline__ void cell_pipeline_mapped(T* __restrict__ B, uint32_t m, int any_hang, T coef,
+                                                     const MapTab<T, K + 1>& mt, const CellGeo<T>& geo,
+                                                     const T* __restrict__ Hg, int ta, int tb, T (&u)[K + 1]) {
+  constexpr int N = K + 1, N2 = N * N;
+  const Sync sync{};
+  const bool hang = mask_hanging(m);
+  auto zl = [&](int c) { return c * N2 + tb * N + ta; };  // z-line (x = ta, y = tb)
+  auto yl = [&](int r) { return tb * N2 + r * N + ta; };  // y-line (x = ta, z = tb)
+  auto xl = [&](int r) { return tb * N2 + ta * N + r; };  // x-line (y = ta, z = tb)
+  if (any_hang) {
+    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, false>(Hg, mask_sub(m, 2), u);
+#pragma unroll
+    for (int c = 0; c < N; ++c) B[zl(c)] = u[c];
+    sync();
+    if (hang && hanging_line(m, 1, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B[yl(r)];
+      interp_lds<N, T, false>(Hg, mask_sub(m, 1), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B[yl(r)] = u[r];
+    }
+    sync();
+    if (hang && hanging_line(m, 0, ta, tb, K)) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) u[r] = B[xl(r)];
+      interp_lds<N, T, false>(Hg, mask_sub(m, 0), u);
+#pragma unroll
+      for (int r = 0; r < N; ++r) B[xl(r)] = u[r];
+    }
+    sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) u[c] = B[zl(c)];
+    sync();
+  }
+  T v[N], w[N], gx[N], gy[N], gz[N];
+  // values at the Gauss points: z, y, x
+  mat_mv<N, T, false>(mt.S, u, v);
+#pragma unroll
+  for (int c = 0; c < N; ++c) B[zl(c)] = v[c];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[r] = B[yl(r)];
+  mat_mv<N, T, false>(mt.S, w, v);
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[yl(r)] = v[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[r] = B[xl(r)];
+  mat_mv<N, T, false>(mt.S, w, v);
+  mat_mv<N, T, false>(mt.D, v, gx);  // d/dxi_1 along this x-line
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[xl(r)] = v[r];
+  sync();
+  // d/dxi_2 (y-lines) and d/dxi_3 (z-lines), brought to this lane's x-line
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[r] = B[yl(r)];
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = B[zl(r)];
+  mat_mv<N, T, false>(mt.D, w, gy);
+  mat_mv<N, T, false>(mt.D, v, gz);
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[yl(r)] = gy[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) gy[r] = B[xl(r)];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[zl(r)] = gz[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) gz[r] = B[xl(r)];
+  // quadrature points (x = r, y = ta, z = tb): flux G grad u
+  {
+    const T t2 = (geo.r[1] + mt.g[ta]) * geo.scale, t3 = (geo.r[2] + mt.g[tb]) * geo.scale;
+    const T wyz = mt.w[ta] * mt.w[tb] * coef;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const T t1 = (geo.r[0] + mt.g[r]) * geo.scale;
+      T J[3][3];
+      geo_jacobian<T>(geo.A, t1, t2, t3, J);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) J[d][e] *= geo.scale;
+      T G[6];
+      geo_metric<T>(J, wyz * mt.w[r], G);
+      const T a = gx[r], b = gy[r], c = gz[r];
+      gx[r] = G[0] * a + G[1] * b + G[2] * c;
+      gy[r] = G[1] * a + G[3] * b + G[4] * c;
+      gz[r] = G[2] * a + G[4] * b + G[5] * c;
+    }
+  }
+  // transposed gradient sweeps, summed along this lane's x-line
+  mat_mv<N, T, true>(mt.D, gx, v);
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[xl(r)] = gy[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[r] = B[yl(r)];
+  mat_mv<N, T, true>(mt.D, w, gy);
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[yl(r)] = gy[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += B[xl(r)];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[xl(r)] = gz[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) w[r] = B[zl(r)];
+  mat_mv<N, T, true>(mt.D, w, gz);
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[zl(r)] = gz[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += B[xl(r)];
+  // back to the nodes: S^T along x, y, z
+  mat_mv<N, T, true>(mt.S, v, w);
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[xl(r)] = w[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = B[yl(r)];
+  mat_mv<N, T, true>(mt.S, v, w);
+#pragma unroll
+  for (int r = 0; r < N; ++r) B[yl(r)] = w[r];
+  sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = B[zl(r)];
+  mat_mv<N, T, true>(mt.S, v, u);
+  if (!any_hang) return;
+  if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 2), u);
+  sync();
+#pragma unroll
+  for (int c = 0; c < N; ++c) B[zl(c)] = u[c];
+  sync();
+  if (hang && hanging_line(m, 1, ta, tb, K)) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[r] = B[yl(r)];
+    interp_lds<N, T, true>(Hg, mask_sub(m, 1), w);
+#pragma unroll
+    for (int r = 0; r < N; ++r) B[yl(r)] = w[r];
+  }
+  sync();
+  if (hang && hanging_line(m, 0, ta, tb, K)) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) w[r] = B[xl(r)];
+    interp_lds<N, T, true>(Hg, mask_sub(m, 0), w);
+#pragma unroll
+    for (int r = 0; r < N; ++r) B[xl(r)] = w[r];
+  }
+  sync();
+#pragma unroll
+  for (int c = 0; c < N; ++c) u[c] = B[zl(c)];
+}
+
+// geometry of cell `cell` of a mapped level (its lattice position ijk and
+// level l; the coarse grid has n0 cells per axis)
+template <typename T>
+__device__ __forceinline__ CellGeo<T> cell_geo(const T* __restrict__ table, const int32_t* __restrict__ ijk,
+                                               int64_t cell, int l, int n0) {
+  CellGeo<T> g;
+  const int i = ijk[3 * cell], j = ijk[3 * cell + 1], k = ijk[3 * cell + 2];
+  const int I = i >> l, J = j >> l, Kc = k >> l;
+  g.A = table + (static_cast<int64_t>(I) + n0 * (J + static_cast<int64_t>(n0) * Kc)) * 24;
+  g.r[0] = static_cast<T>(i - (I << l));
+  g.r[1] = static_cast<T>(j - (J << l));
+  g.r[2] = static_cast<T>(k - (Kc << l));
+  g.scale = static_cast<T>(ldexp(1.0, -l));
+  return g;
+}
+
 // Final value t = (A x) of DoF g, vector v, and the fused step applied to it
 template <typename S, typename T, int FK>
 __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv, int v, T t, T* __restrict__ dst) {
@@ -559,21 +801,24 @@ __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv
 // their contributions accumulated in LDS, then the exclusive DoFs are stored
 // contiguously and the shared DoFs written as this batch's partial sums
 // (reduced afterwards).  gridDim.x is a multiple of 8.
-// register budget: the fused variants up to degree 4 are held to 4
-// wavefronts per SIMD (two blocks per CU, as the LDS allows); elsewhere the
-// compiler's own allocation is kept
-template <int K, int FK>
+// register budget: 4 wavefronts per SIMD (two blocks per CU, as the LDS
+// allows); the operator of mapped cells, which holds three gradient
+// components and the metric terms of a line of points, gets the registers of
+// 2 wavefronts per SIMD instead of spilling
+template <int K, int FK, int GEO>
 struct BatchWavesPerEu {
-  static constexpr int value = (FK != FUSE_NONE && K <= 4) ? 4 : 1;
+  static constexpr int value = GEO ? 2 : 4;
 };
 
-template <int K, typename S, typename T, int FK>
-__global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_per_eu(BatchWavesPerEu<K, FK>::value)))
+template <int K, typename S, typename T, int FK, int GEO>
+__global__ void __launch_bounds__(BATCH_WAVES * 64)
+    __attribute__((amdgpu_waves_per_eu(BatchWavesPerEu<K, FK, GEO>::value)))
     vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
                        const int32_t* __restrict__ bsh, const int32_t* __restrict__ bex,
                        const int32_t* __restrict__ sh_idx, int64_t nb,
                        int64_t n_shared, double h0, OpTab2<T, K + 1> tab, const S* __restrict__ src,
-                       T* __restrict__ partial, T* __restrict__ dst, int nv, FusedStep fs) {
+                       T* __restrict__ partial, T* __restrict__ dst, int nv, FusedStep fs,
+                       const T* __restrict__ geo, const int32_t* __restrict__ ijk, int n0, MapTab<T, K + 1> mt) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, CPW = cells_per_wave(N), MCAP = batch_mcap(K);
   constexpr int NZ = batch_zero_entries(K), ZB = MCAP;  // zero block behind the batch's DoFs
   constexpr int BT = BATCH_WAVES * 64, PER = (MCAP + BT - 1) / BT;
@@ -583,7 +828,6 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
   constexpr bool META_LDS = batch_meta_in_lds(K);
   __shared__ CellMeta metaL[META_LDS ? batch_max_cells(K) : 1];
   __shared__ T buf0[(BATCH_WAVES * CPW + 1) * N3];
-  __shared__ T buf1[(BATCH_WAVES * CPW + 1) * N3];
   for (int i = threadIdx.x; i < NZ; i += BT) in_[ZB + i] = T(0);
   for (int i = threadIdx.x; i < 2 * N2; i += BT) Hg[i] = tab.Hg[i];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -593,7 +837,6 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
   const int ta = t % N, tb = t / N;
   // lanes without a cell work on the block's spare buffers (results unused)
   T* B0 = buf0 + (lane_used ? wave * CPW + lc : BATCH_WAVES * CPW) * N3;
-  T* B1 = buf1 + (lane_used ? wave * CPW + lc : BATCH_WAVES * CPW) * N3;
   const LaneLines ll = kLaneLines<K>.t[t];
   const int gs0 = ll.zs0, gs1 = ll.zs1, gsm = ll.zsm, go0 = ll.zo0, gom = ll.zom, gst = ll.zst;
   const int ss0 = ll.xs0, ss1 = ll.xs1, ssm = ll.xsm, so0 = ll.xo0, som = ll.xom, sst = ll.xst;
@@ -621,17 +864,17 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
     // stage the batch's DoFs: all index loads of a thread, then all value
     // loads, then the LDS stores, so that the loads of a thread overlap
     {
-      int64_t gi[PER];
+      int32_t gi[PER];  // DoF indices (a level has fewer than 2^31 DoFs)
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int i = threadIdx.x + q * BT;
-        gi[q] = i < nsh ? static_cast<int64_t>(sh_idx[sh0 + i]) : ex0 + (i - nsh);
+        gi[q] = i < nsh ? sh_idx[sh0 + i] : static_cast<int32_t>(ex0 + (i - nsh));
       }
       T val[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int i = threadIdx.x + q * BT;
-        val[q] = i < m ? load_as<T>(src[gi[q] * nv + v]) : T(0);
+        val[q] = i < m ? load_as<T>(src[static_cast<int64_t>(gi[q]) * nv + v]) : T(0);
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
@@ -683,7 +926,14 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64) __attribute__((amdgpu_waves_
 #pragma unroll
         for (int c = 1; c < K; ++c) u[c] = in_[cur.gm + gom + (c - 1) * gst];
       }
-      const bool zline = cell_pipeline_zfirst<K, T, WaveSync>(B0, B1, mk, wave_hang, h, tab, Hg, ta, tb, u);
+      bool zline = true;
+      if constexpr (GEO != 0) {  // mapped cell: its own map from its coarse cell
+        const int64_t cell = (lane_used && cw + lc < c1) ? cw + lc : c0;
+        const CellGeo<T> g = cell_geo<T>(geo, ijk, cell, mask_level(mk), n0);
+        cell_pipeline_mapped<K, T, WaveSync>(B0, mk, wave_hang, static_cast<T>(mask_coef(mk)), mt, g, Hg, ta, tb, u);
+      } else {
+        zline = cell_pipeline_zfirst<K, T, WaveSync>(B0, mk, wave_hang, h, tab, Hg, ta, tb, u);
+      }
       // scatter-add along the result line, skipping absent entities and
       // lanes without a cell (they point at the zero block); a line through
       // the cell interior (slot 26) holds DoFs of this cell only
@@ -777,6 +1027,144 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   scatter_yline<K>(ent, nc, cell, ta, tb, d, diag, 1, 0);
 }
 
+// scatter-add of the line of nodes (a, b, 0..k) (along z), as scatter_yline
+template <int K, typename T>
+__device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell, int a,
+                                              int b, const T (&w)[K + 1], T* __restrict__ dst) {
+  const int s0 = node_slot(a, b, 0, K), s1 = node_slot(a, b, K, K);
+  const int o0 = node_offset(a, b, 0, K);
+  const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
+  if (e0 >= 0) atomic_add(&dst[e0 + o0], w[0]);
+  if (e1 >= 0) atomic_add(&dst[e1 + o0], w[K]);
+  if constexpr (K > 1) {
+    const int sm = node_slot(a, b, 1, K);
+    const int om = node_offset(a, b, 1, K);
+    const int st = K > 2 ? node_offset(a, b, 2, K) - om : 0;
+    const int32_t em = ent[sm * nc + cell];
+    if (em >= 0) {
+#pragma unroll
+      for (int c = 1; c < K; ++c) {
+        if (sm == 26) dst[em + om + (c - 1) * st] = w[c];
+        else atomic_add(&dst[em + om + (c - 1) * st], w[c]);
+      }
+    }
+  }
+}
+
+// Diagonal of a mapped cell without constraints, A_e(i,i) =
+// sum_q grad phi_i(q)^T G_q grad phi_i(q), G_q = c_e w_q |det J| J^-1 J^-T:
+// with phi_i = l_a l_b l_c, d_xi1 phi_i = l'_a l_b l_c etc., every product of
+// two gradient components is a product of 1D factors, so the six symmetric
+// components of G contract with squared 1D tables (E = S.S, F = S'.S',
+// X = S'.S elementwise; S' = l'(g_q)) axis by axis: 6 x 3 sweeps.  One cell
+// per block of n^2 threads; cells with hanging nodes are left to
+// diag_mapped_kernel.
+template <typename T, int N>
+struct DiagTab {
+  T E[N * N], F[N * N], X[N * N];  // [q][a]
+};
+
+template <int K>
+__global__ void __launch_bounds__((K + 1) * (K + 1))
+    diag_mapped_direct_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
+                              const double* __restrict__ geo, const int32_t* __restrict__ ijk, int n0,
+                              MapTab<double, K + 1> mt, DiagTab<double, K + 1> dt, double* __restrict__ diag) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
+  __shared__ double B[N3];
+  const int64_t cell = blockIdx.x;
+  const uint32_t m = mask[cell];
+  if (mask_hanging(m)) return;
+  const int ta = threadIdx.x % N, tb = threadIdx.x / N;
+  const CellGeo<double> g = cell_geo<double>(geo, ijk, cell, mask_level(m), n0);
+  const double coef = static_cast<double>(mask_coef(m));
+  double G[6][N];  // this lane's x-line of quadrature points (x = r, y = ta, z = tb)
+  {
+    const double t2 = (g.r[1] + mt.g[ta]) * g.scale, t3 = (g.r[2] + mt.g[tb]) * g.scale;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      double J[3][3], Gq[6];
+      geo_jacobian<double>(g.A, (g.r[0] + mt.g[r]) * g.scale, t2, t3, J);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) J[d][e] *= g.scale;
+      geo_metric<double>(J, coef * mt.w[r] * mt.w[ta] * mt.w[tb], Gq);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) G[q][r] = Gq[q];
+    }
+  }
+  // (component of G, factor, x table, y table, z table): g00 F E E, g11 E F E,
+  // g22 E E F, 2 g01 X X E, 2 g02 X E X, 2 g12 E X X
+  const double* tabs[6][3] = {{dt.F, dt.E, dt.E}, {dt.X, dt.X, dt.E}, {dt.X, dt.E, dt.X},
+                              {dt.E, dt.F, dt.E}, {dt.E, dt.X, dt.X}, {dt.E, dt.E, dt.F}};
+  const double fac[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double d[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) d[c] = 0.0;
+  for (int q = 0; q < 6; ++q) {
+    double v[N], w[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = fac[q] * G[q][r];
+    mat_mv<N, double, true>(tabs[q][0], v, w);  // x: node a <- point
+    WaveSync{}();
+#pragma unroll
+    for (int r = 0; r < N; ++r) B[tb * N2 + ta * N + r] = w[r];
+    WaveSync{}();
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = B[tb * N2 + r * N + ta];
+    mat_mv<N, double, true>(tabs[q][1], v, w);  // y
+#pragma unroll
+    for (int r = 0; r < N; ++r) B[tb * N2 + r * N + ta] = w[r];
+    WaveSync{}();
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = B[r * N2 + tb * N + ta];
+    mat_mv<N, double, true>(tabs[q][2], v, w);  // z
+#pragma unroll
+    for (int c = 0; c < N; ++c) d[c] += w[c];
+  }
+  scatter_zline<K>(ent, nc, cell, ta, tb, d, diag);
+}
+
+// Diagonal of a mapped cell with hanging nodes (Eq. impl:mf:diagonal): the
+// cell operator C_e^T A_e C_e applied to every unit slot vector e_s, entry s
+// kept.  One cell per block of n^2 threads (one wavefront).
+template <int K>
+__global__ void __launch_bounds__((K + 1) * (K + 1))
+    diag_mapped_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
+                       const double* __restrict__ geo, const int32_t* __restrict__ ijk, int n0,
+                       MapTab<double, K + 1> mt, OpTab2<double, K + 1> tab, double* __restrict__ diag) {
+  constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
+  __shared__ double B[N3];
+  __shared__ double Hg[2 * N2];
+  for (int i = threadIdx.x; i < 2 * N2; i += blockDim.x) Hg[i] = tab.Hg[i];
+  __syncthreads();
+  const int64_t cell = blockIdx.x;
+  const int ta = threadIdx.x % N, tb = threadIdx.x / N;
+  const uint32_t m = mask[cell];
+  if (!mask_hanging(m)) return;  // (diag_mapped_direct_kernel)
+  const CellGeo<double> g = cell_geo<double>(geo, ijk, cell, mask_level(m), n0);
+  const double coef = static_cast<double>(mask_coef(m));
+  const int any_hang = 1;
+  double d[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) d[c] = 0.0;
+  for (int sc = 0; sc < N; ++sc)
+    for (int sb = 0; sb < N; ++sb)
+      for (int sa = 0; sa < N; ++sa) {
+        double u[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) u[c] = (ta == sa && tb == sb && c == sc) ? 1.0 : 0.0;
+        cell_pipeline_mapped<K, double, WaveSync>(B, m, any_hang, coef, mt, g, Hg, ta, tb, u);
+        if (ta == sa && tb == sb) {
+#pragma unroll
+          for (int c = 0; c < N; ++c)
+            if (c == sc) d[c] += u[c];
+        }
+        WaveSync{}();
+      }
+  scatter_zline<K>(ent, nc, cell, ta, tb, d, diag);
+}
+
 // Constraint distribution: gather G_e and hanging-node interpolation C_e of
 // one cell, written out node by node.  One cell per block, n^2 threads.
 template <int K>
@@ -823,7 +1211,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
     rhs_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask,
                const int32_t* __restrict__ cell_ijk, int64_t nc, double h0, double lo, OpTab<double, K + 1> tab,
                Gauss1D<K + 1> g, int kind, const double* __restrict__ params, int n_terms, double* __restrict__ b,
-               int nv) {
+               int nv, const double* __restrict__ geo, int n0) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
   __shared__ double B0[N3];
   const int64_t cell = blockIdx.x;
@@ -837,9 +1225,26 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   const double z0 = lo + h * cell_ijk[3 * cell + 2];
   // z-line of quadrature points (qx = ta, qy = tb): weighted f values
   double gz[N];
+  CellGeo<double> cg{};
+  if (geo) cg = cell_geo<double>(geo, cell_ijk, cell, lev, n0);
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     double x = x0 + h * g.x[ta], y = y0 + h * g.x[tb], z = z0 + h * g.x[q];
+    double vol = h * h * h;  // |det J| of the cell map
+    if (geo) {  // mapped cell: physical point and |det J| from its map
+      const double t1 = (cg.r[0] + g.x[ta]) * cg.scale, t2 = (cg.r[1] + g.x[tb]) * cg.scale,
+                   t3 = (cg.r[2] + g.x[q]) * cg.scale;
+      double X[3], J[3][3];
+      geo_point<double>(cg.A, t1, t2, t3, X);
+      geo_jacobian<double>(cg.A, t1, t2, t3, J);
+      x = X[0];
+      y = X[1];
+      z = X[2];
+      vol = (J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+             J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0])) *
+            cg.scale * cg.scale * cg.scale;
+      vol = vol < 0 ? -vol : vol;
+    }
     double f = 0.0;
     if (kind == 0) {
       f = params[0];
@@ -852,7 +1257,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
         f += p[5 * t + 4] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * w * w));
       }
     }
-    gz[q] = f * g.w[ta] * g.w[tb] * g.w[q] * h * h * h;
+    gz[q] = f * g.w[ta] * g.w[tb] * g.w[q] * vol;
   }
   // S^T along z: out[c] = sum_q S[q][c] gz[q]
   double u[N];
@@ -917,7 +1322,7 @@ namespace mfmg {
 
 // ---------------------------------------------------------------------------
 // Intergrid transfer (Section 3.5, Eq. eq:impl:loop:categorized): one coarse
-// cell (transfer group) per block of 64 threads.  Prolongation:
+// cell (transfer group) per block.  Prolongation:
 //   coarse gather G_c with constraints C_c (in-place interpolation),
 //   category prolongation P (three 1D sweeps; identity category: none),
 //   weights W = 1/valence (0 for constrained fine DoFs), scatter S_f.
@@ -926,40 +1331,55 @@ namespace mfmg {
 // Lattice of a group: NF nodes per axis.  Refinement category: NF = 2k+1
 // nodes covering the 8 children (child along an axis = node index >= k);
 // polynomial category: NF = k_f+1; identity: NF = NC, no sweeps.
-constexpr int TR_THREADS = 64;
+//
+// Several interleaved vectors are handled VB at a time: the vector index is
+// the fastest one of the threads and of the LDS arrays ([node][VB]), so the
+// VB values of a DoF, adjacent in memory, are read and written by adjacent
+// threads.  VB is the largest power of two <= 8 whose arrays fit 32 KB.
+constexpr int TR_THREADS = 256;
 
-template <int KC, typename T>
+template <int NF, int NC, typename T>
+constexpr int transfer_vb() {
+  constexpr int per = (NC * NC * NC + NF * NC * NC + NF * NF * NC + NF * NF * NF) * static_cast<int>(sizeof(T));
+  return per * 8 <= 32768 ? 8 : per * 4 <= 32768 ? 4 : per * 2 <= 32768 ? 2 : 1;
+}
+
+// in-place hanging-node interpolation of the coarse cell's node values
+// X[node][VB] (vectors vv < nb)
+template <int KC, int VB, typename T>
 __device__ __forceinline__ void constraints_lds(T* X, uint32_t m, const T (&H)[2][(KC + 1) * (KC + 1)],
-                                                bool trans) {
+                                                bool trans, int nb) {
   constexpr int N = KC + 1, N2 = N * N;
   for (int d = 0; d < 3; ++d) {
     __syncthreads();
     const int s = mask_sub(m, d);
-    for (int line = threadIdx.x; line < N2; line += blockDim.x) {
+    for (int t = threadIdx.x; t < N2 * nb; t += blockDim.x) {
+      const int line = t / nb, vv = t - line * nb;
       const int p = line % N, q = line / N;
       if (!hanging_line(m, d, p, q, KC)) continue;
       T u[N];
       const int stride = d == 0 ? 1 : d == 1 ? N : N2;
       const int base = d == 0 ? p * N + q * N2 : d == 1 ? p + q * N2 : p + q * N;
 #pragma unroll
-      for (int r = 0; r < N; ++r) u[r] = X[base + r * stride];
+      for (int r = 0; r < N; ++r) u[r] = X[(base + r * stride) * VB + vv];
       if (trans) interp<N, T, true>(H, s, u);
       else interp<N, T, false>(H, s, u);
 #pragma unroll
-      for (int r = 0; r < N; ++r) X[base + r * stride] = u[r];
+      for (int r = 0; r < N; ++r) X[(base + r * stride) * VB + vv] = u[r];
     }
   }
   __syncthreads();
 }
 
-// out (NO along axis d) = P (NO x NI) applied along axis d of `in`; other
-// axes: sizes n_other0 (the lower axis) and n_other1
-template <int NI, int NO, typename T, bool TRANS>
-__device__ __forceinline__ void sweep_lds(const T* in, T* out, const T* __restrict__ P, int d, int na, int nb) {
-  // `in` has extent NI along d, `out` NO along d; the other two axes (in
-  // increasing order) have extents na, nb in both.  Layout x fastest.
+// out (NO along axis d) = P (NO x NI) applied along axis d of `in`; the
+// other two axes (in increasing order) have extents na, nb in both; layout x
+// fastest, then the VB vectors innermost
+template <int NI, int NO, int VB, typename T, bool TRANS>
+__device__ __forceinline__ void sweep_lds(const T* in, T* out, const T* __restrict__ P, int d, int na, int nb,
+                                          int nvb) {
   const int lines = na * nb;
-  for (int line = threadIdx.x; line < lines; line += blockDim.x) {
+  for (int t = threadIdx.x; t < lines * nvb; t += blockDim.x) {
+    const int line = t / nvb, vv = t - line * nvb;
     const int p = line % na, q = line / na;
     int sin, sout, bin, bout;
     if (d == 0) { sin = 1; sout = 1; bin = (p + q * na) * NI; bout = (p + q * na) * NO; }
@@ -967,13 +1387,13 @@ __device__ __forceinline__ void sweep_lds(const T* in, T* out, const T* __restri
     else { sin = na * nb; sout = na * nb; bin = p + q * na; bout = p + q * na; }
     T u[NI];
 #pragma unroll
-    for (int r = 0; r < NI; ++r) u[r] = in[bin + r * sin];
+    for (int r = 0; r < NI; ++r) u[r] = in[(bin + r * sin) * VB + vv];
 #pragma unroll
     for (int i = 0; i < NO; ++i) {
       T acc = T(0);
 #pragma unroll
       for (int j = 0; j < NI; ++j) acc += (TRANS ? P[j * NO + i] : P[i * NI + j]) * u[j];
-      out[bout + i * sout] = acc;
+      out[(bout + i * sout) * VB + vv] = acc;
     }
   }
 }
@@ -999,50 +1419,53 @@ __global__ void __launch_bounds__(TR_THREADS)
                       S* __restrict__ dst, int nv) {
   constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
   constexpr bool IDENT = (NF == NC) && (KF == KC);
-  __shared__ T X[NC3];
-  __shared__ T Y1[IDENT ? 1 : NF * NC * NC];
-  __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
-  __shared__ T Y3[IDENT ? 1 : NF3];
+  constexpr int VB = transfer_vb<NF, NC, T>();
+  __shared__ T X[NC3 * VB];
+  __shared__ T Y1[IDENT ? 1 : NF * NC * NC * VB];
+  __shared__ T Y2[IDENT ? 1 : NF * NF * NC * VB];
+  __shared__ T Y3[IDENT ? 1 : NF3 * VB];
   const int64_t g = blockIdx.x;
   const int64_t cc = group_coarse[g];
   const uint32_t mc = cmask[cc];
-  // the vectors one after the other in the same block: the interleaved
-  // values of a DoF share cache lines
-  for (int v = 0; v < nv; ++v) {
-  if (v > 0) __syncthreads();
-  for (int i = threadIdx.x; i < NC3; i += blockDim.x) {
-    const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
-    const int s = node_slot(a, b, c, KC);
-    const int32_t e = cent[s * ncc + cc];
-    X[i] = e < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v]);
-  }
-  if (mask_hanging(mc)) constraints_lds<KC, T>(X, mc, tab.H, false);
-  else __syncthreads();
-  const T* Y = X;
-  if constexpr (!IDENT) {
-    sweep_lds<NC, NF, T, false>(X, Y1, tab.P, 0, NC, NC);
-    __syncthreads();
-    sweep_lds<NC, NF, T, false>(Y1, Y2, tab.P, 1, NF, NC);
-    __syncthreads();
-    sweep_lds<NC, NF, T, false>(Y2, Y3, tab.P, 2, NF, NF);
-    __syncthreads();
-    Y = Y3;
-  }
-  for (int i = threadIdx.x; i < NF3; i += blockDim.x) {
-    const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
-    int cx, cy, cz, a, b, c;
-    lattice_local<KF, NF>(I, cx, a);
-    lattice_local<KF, NF>(J, cy, b);
-    lattice_local<KF, NF>(L, cz, c);
-    const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
-    const int64_t f = group_fine[child * ngroups + g];
-    const int s = node_slot(a, b, c, KF);
-    const int val = valence[s * nfc + f];
-    if (val == 0) continue;
-    const int32_t e = fent[s * nfc + f];
-    const int64_t idx = static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v;
-    add_to<S, T>(&dst[idx], Y[i] / static_cast<T>(val), val == 1);
-  }
+  for (int v0 = 0; v0 < nv; v0 += VB) {
+    const int nb = nv - v0 < VB ? nv - v0 : VB;
+    if (v0 > 0) __syncthreads();
+    for (int t = threadIdx.x; t < NC3 * nb; t += blockDim.x) {
+      const int i = t / nb, vv = t - i * nb;
+      const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
+      const int s = node_slot(a, b, c, KC);
+      const int32_t e = cent[s * ncc + cc];
+      X[i * VB + vv] =
+          e < 0 ? T(0) : load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v0 + vv]);
+    }
+    if (mask_hanging(mc)) constraints_lds<KC, VB, T>(X, mc, tab.H, false, nb);
+    else __syncthreads();
+    const T* Y = X;
+    if constexpr (!IDENT) {
+      sweep_lds<NC, NF, VB, T, false>(X, Y1, tab.P, 0, NC, NC, nb);
+      __syncthreads();
+      sweep_lds<NC, NF, VB, T, false>(Y1, Y2, tab.P, 1, NF, NC, nb);
+      __syncthreads();
+      sweep_lds<NC, NF, VB, T, false>(Y2, Y3, tab.P, 2, NF, NF, nb);
+      __syncthreads();
+      Y = Y3;
+    }
+    for (int t = threadIdx.x; t < NF3 * nb; t += blockDim.x) {
+      const int i = t / nb, vv = t - i * nb;
+      const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
+      int cx, cy, cz, a, b, c;
+      lattice_local<KF, NF>(I, cx, a);
+      lattice_local<KF, NF>(J, cy, b);
+      lattice_local<KF, NF>(L, cz, c);
+      const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
+      const int64_t f = group_fine[child * ngroups + g];
+      const int s = node_slot(a, b, c, KF);
+      const int val = valence[s * nfc + f];
+      if (val == 0) continue;
+      const int32_t e = fent[s * nfc + f];
+      const int64_t idx = static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v0 + vv;
+      add_to<S, T>(&dst[idx], Y[i * VB + vv] / static_cast<T>(val), val == 1);
+    }
   }
 }
 
@@ -1055,52 +1478,56 @@ __global__ void __launch_bounds__(TR_THREADS)
                     S* __restrict__ dst, int nv) {
   constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
   constexpr bool IDENT = (NF == NC) && (KF == KC);
-  __shared__ T X[NC3];
-  __shared__ T Y1[IDENT ? 1 : NF * NC * NC];
-  __shared__ T Y2[IDENT ? 1 : NF * NF * NC];
-  __shared__ T Y3[IDENT ? 1 : NF3];
+  constexpr int VB = transfer_vb<NF, NC, T>();
+  __shared__ T X[NC3 * VB];
+  __shared__ T Y1[IDENT ? 1 : NF * NC * NC * VB];
+  __shared__ T Y2[IDENT ? 1 : NF * NF * NC * VB];
+  __shared__ T Y3[IDENT ? 1 : NF3 * VB];
   const int64_t g = blockIdx.x;
   const int64_t cc = group_coarse[g];
   const uint32_t mc = cmask[cc];
-  // the vectors one after the other in the same block: the interleaved
-  // values of a DoF share cache lines
-  for (int v = 0; v < nv; ++v) {
-  if (v > 0) __syncthreads();
-  T* Yw = IDENT ? X : Y3;
-  for (int i = threadIdx.x; i < NF3; i += blockDim.x) {
-    const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
-    int cx, cy, cz, a, b, c;
-    lattice_local<KF, NF>(I, cx, a);
-    lattice_local<KF, NF>(J, cy, b);
-    lattice_local<KF, NF>(L, cz, c);
-    const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
-    const int64_t f = group_fine[child * ngroups + g];
-    const int s = node_slot(a, b, c, KF);
-    const int val = valence[s * nfc + f];
-    T y = T(0);
-    if (val) {
-      const int32_t e = fent[s * nfc + f];
-      y = load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v]) / static_cast<T>(val);
+  for (int v0 = 0; v0 < nv; v0 += VB) {
+    const int nb = nv - v0 < VB ? nv - v0 : VB;
+    if (v0 > 0) __syncthreads();
+    T* Yw = IDENT ? X : Y3;
+    for (int t = threadIdx.x; t < NF3 * nb; t += blockDim.x) {
+      const int i = t / nb, vv = t - i * nb;
+      const int I = i % NF, J = (i / NF) % NF, L = i / (NF * NF);
+      int cx, cy, cz, a, b, c;
+      lattice_local<KF, NF>(I, cx, a);
+      lattice_local<KF, NF>(J, cy, b);
+      lattice_local<KF, NF>(L, cz, c);
+      const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
+      const int64_t f = group_fine[child * ngroups + g];
+      const int s = node_slot(a, b, c, KF);
+      const int val = valence[s * nfc + f];
+      T y = T(0);
+      if (val) {
+        const int32_t e = fent[s * nfc + f];
+        y = load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v0 + vv]) /
+            static_cast<T>(val);
+      }
+      Yw[i * VB + vv] = y;
     }
-    Yw[i] = y;
-  }
-  __syncthreads();
-  if constexpr (!IDENT) {
-    sweep_lds<NF, NC, T, true>(Y3, Y2, tab.P, 2, NF, NF);
     __syncthreads();
-    sweep_lds<NF, NC, T, true>(Y2, Y1, tab.P, 1, NF, NC);
-    __syncthreads();
-    sweep_lds<NF, NC, T, true>(Y1, X, tab.P, 0, NC, NC);
-    __syncthreads();
-  }
-  if (mask_hanging(mc)) constraints_lds<KC, T>(X, mc, tab.H, true);
-  for (int i = threadIdx.x; i < NC3; i += blockDim.x) {
-    const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
-    const int s = node_slot(a, b, c, KC);
-    const int32_t e = cent[s * ncc + cc];
-    if (e < 0) continue;
-    add_to<S, T>(&dst[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v], X[i], s == 26);
-  }
+    if constexpr (!IDENT) {
+      sweep_lds<NF, NC, VB, T, true>(Y3, Y2, tab.P, 2, NF, NF, nb);
+      __syncthreads();
+      sweep_lds<NF, NC, VB, T, true>(Y2, Y1, tab.P, 1, NF, NC, nb);
+      __syncthreads();
+      sweep_lds<NF, NC, VB, T, true>(Y1, X, tab.P, 0, NC, NC, nb);
+      __syncthreads();
+    }
+    if (mask_hanging(mc)) constraints_lds<KC, VB, T>(X, mc, tab.H, true, nb);
+    for (int t = threadIdx.x; t < NC3 * nb; t += blockDim.x) {
+      const int i = t / nb, vv = t - i * nb;
+      const int a = i % NC, b = (i / NC) % NC, c = i / (NC * NC);
+      const int s = node_slot(a, b, c, KC);
+      const int32_t e = cent[s * ncc + cc];
+      if (e < 0) continue;
+      add_to<S, T>(&dst[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v0 + vv], X[i * VB + vv],
+                   s == 26);
+    }
   }
 }
 
@@ -1324,12 +1751,15 @@ void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
   check_launch();
 }
 
-template <int K, typename S, int FK>
-void vmult_k(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+template <int K, typename S, int FK, int GEO>
+void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
   using T = typename Acc<S>::type;
   constexpr int N = K + 1;
   if (c.n_cells == 0) return;
   static const OpTab2<T, N> tab = make_optab2<T, N>();
+  static const MapTab<T, N> mt = make_maptab<T, N>();
+  const T* geo = nullptr;
+  if constexpr (GEO != 0) geo = static_cast<const T*>(sizeof(T) == 8 ? c.geo64 : c.geo32);
   // persistent blocks: as many as are resident on the device at once (a
   // multiple of 8, one share per XCD), at most one per batch
   static const int64_t resident = [] {
@@ -1337,7 +1767,8 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, const FusedS
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T, FK>), BATCH_WAVES * 64, 0) != hipSuccess) {
+            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T, FK, GEO>), BATCH_WAVES * 64, 0) !=
+            hipSuccess) {
       (void)hipGetLastError();
       return int64_t(0);
     }
@@ -1346,15 +1777,21 @@ void vmult_k(const CellView& c, int nv, void* dst, const void* src, const FusedS
   const int64_t nb = c.n_batches;
   int64_t blocks = 8 * ((nb + 7) / 8);
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
-  vmult_batch_kernel<K, S, T, FK><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
+  vmult_batch_kernel<K, S, T, FK, GEO><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
-      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f);
+      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0, mt);
   check_launch();
   if (c.n_shared > 0) {
     reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
         c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
     check_launch();
   }
+}
+
+template <int K, typename S, int FK>
+void vmult_k(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+  if (c.geo64) vmult_kg<K, S, FK, 1>(c, nv, dst, src, f, s);
+  else vmult_kg<K, S, FK, 0>(c, nv, dst, src, f, s);
 }
 
 template <int K, typename S>
@@ -1385,6 +1822,30 @@ void diag_k(const CellView& c, double* diag, hipStream_t s) {
   constexpr int N = K + 1;
   zero_bytes(diag, c.n_dofs * 8, s);
   if (c.n_cells == 0) return;
+  if (c.geo64) {
+    static const MapTab<double, N> mt = make_maptab<double, N>();
+    static const OpTab2<double, N> tab2 = make_optab2<double, N>();
+    static const DiagTab<double, N> dt = [] {
+      const Tables1D& t = tables(N - 1);
+      DiagTab<double, N> r;
+      for (int q = 0; q < N; ++q)
+        for (int a = 0; a < N; ++a) {
+          const double sv = t.S[q * N + a], dv = lagrange_deriv(t.nodes, a, t.qp[q]);
+          r.E[q * N + a] = sv * sv;
+          r.F[q * N + a] = dv * dv;
+          r.X[q * N + a] = dv * sv;
+        }
+      return r;
+    }();
+    const double* geo = static_cast<const double*>(c.geo64);
+    diag_mapped_direct_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(
+        c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, dt, diag);
+    check_launch();
+    diag_mapped_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(
+        c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, tab2, diag);
+    check_launch();
+    return;
+  }
   static const OpTab<double, N> tab = make_optab<double, N>();
   diag_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab, diag);
   check_launch();
@@ -1399,7 +1860,7 @@ void rhs_k(const CellView& c, int kind, const double* params, int n_terms, int n
   static const Gauss1D<N> g = make_gauss<N>();
   dim3 grid(static_cast<unsigned>(c.n_cells), nv);
   rhs_kernel<K><<<grid, N * N, 0, s>>>(c.ent, c.mask, c.ijk, c.n_cells, c.h0, c.lo, tab, g, kind, params,
-                                       n_terms, b, nv);
+                                       n_terms, b, nv, static_cast<const double*>(c.geo64), c.geo_n0);
   check_launch();
 }
 

@@ -37,6 +37,11 @@ struct CellView {
   const int32_t* red_idx = nullptr;
   const int32_t* red_off = nullptr;
   void* partial = nullptr;            // scratch: partial sums, (sh_idx size) x max_rhs x 8 bytes
+  // mapped cells (geometry.hpp): coarse-cell map coefficients in FP64 and
+  // FP32 ([n0^3][24]), NULL for axis-aligned cubes; n0 coarse cells per axis
+  const void* geo64 = nullptr;
+  const void* geo32 = nullptr;
+  int geo_n0 = 0;
 };
 
 // An elementwise step fused into the operator's output: for every DoF i and

@@ -94,10 +94,10 @@ constexpr bool BATCH_QUANTIZE = MFMG_BATCH_QUANTIZE != 0;
 constexpr int BATCH_GRID_FACTOR = MFMG_BATCH_GRID_FACTOR;
 __host__ __device__ constexpr int batch_zero_entries(int k) { return k > 1 ? (k - 1) * (k - 1) * (k - 1) : 1; }
 __host__ __device__ constexpr int batch_work_bytes(int k) {
-  // two n^3 buffers per cell of every wavefront plus one spare pair for lanes
+  // one n^3 buffer per cell of every wavefront plus a spare one for lanes
   // without a cell, the hanging-interpolation matrices of both halves and the
   // staged cell metadata
-  return (BATCH_WAVES * cells_per_wave(k + 1) + 1) * 2 * (k + 1) * (k + 1) * (k + 1) * 8 + 2 * (k + 1) * (k + 1) * 8 +
+  return (BATCH_WAVES * cells_per_wave(k + 1) + 1) * (k + 1) * (k + 1) * (k + 1) * 8 + 2 * (k + 1) * (k + 1) * 8 +
          (batch_meta_in_lds(k) ? batch_max_cells(k) * 64 : 0);
 }
 __host__ __device__ constexpr int batch_mcap(int k) {

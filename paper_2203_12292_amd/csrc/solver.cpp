@@ -251,6 +251,11 @@ void init_level(Context& ctx, Level& L, const LevelDofs& H, double lo, bool work
   L.view.red_idx = L.red_idx.ptr;
   L.view.red_off = L.red_off.ptr;
   L.view.partial = L.partial.ptr;
+  if (ctx.geo.kind != 0) {
+    L.view.geo64 = ctx.geo64.ptr;
+    L.view.geo32 = ctx.geo32.ptr;
+    L.view.geo_n0 = ctx.geo_n0;
+  }
   const int64_t nrhs = L.n_dofs * ctx.max_rhs;
   const size_t sb = dtype_size(L.dtype);
   if (work) {
@@ -380,6 +385,31 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
                MFMG_ERR_UNSUPPORTED, "full multigrid runs on global-coarsening levels");
   ctx.stream = s;
   ctx.meshes = mesh.gc;
+  ctx.geo.kind = desc.geom_kind;
+  for (int i = 0; i < 8; ++i) ctx.geo.p[i] = desc.geom_params[i];
+  MFMG_REQUIRE(desc.geom_kind >= 0 && desc.geom_kind <= 2, MFMG_ERR_INVALID_ARG, "unknown geometry kind");
+  if (ctx.geo.kind != 0) {
+    MFMG_REQUIRE(desc.scheme != MFMG_SCHEME_LS && desc.scheme != MFMG_SCHEME_LS_THEN_P, MFMG_ERR_UNSUPPORTED,
+                 "mapped cells are built for global-coarsening levels");
+    const Octree& g0 = ctx.meshes[0];
+    ctx.geo_n0 = g0.n0;
+    ctx.geo_host = geometry_table(ctx.geo, g0.n0, g0.lo, g0.hi);
+    // every coarse-cell map must keep its orientation (det J > 0 at the
+    // corners and the centre of each coarse cell)
+    for (size_t c = 0; c * 24 < ctx.geo_host.size(); ++c)
+      for (int q = 0; q < 9; ++q) {
+        const double t1 = q < 8 ? (q & 1) : 0.5, t2 = q < 8 ? ((q >> 1) & 1) : 0.5, t3 = q < 8 ? ((q >> 2) & 1) : 0.5;
+        double J[3][3];
+        geo_jacobian<double>(&ctx.geo_host[c * 24], t1, t2, t3, J);
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        MFMG_REQUIRE(det > 0.0, MFMG_ERR_INVALID_ARG, "geometry: a coarse cell map is not orientation preserving");
+      }
+    ctx.geo64.upload(ctx.geo_host);
+    std::vector<float> g32(ctx.geo_host.begin(), ctx.geo_host.end());
+    ctx.geo32.upload(g32);
+  }
   ctx.max_rhs = desc.max_rhs > 0 ? desc.max_rhs : 1;
   MFMG_REQUIRE(ctx.max_rhs <= 8, MFMG_ERR_UNSUPPORTED, "max_rhs must be <= 8");
   ctx.cheb_degree = desc.cheb_degree > 0 ? desc.cheb_degree : 3;
@@ -422,7 +452,8 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     ctx.n0 = L0.n_dofs;
     if (desc.dirichlet) {  // (the pure Neumann coarse matrix is singular)
       MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
-      std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k));
+      std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k), ctx.geo.kind ? &ctx.geo_host : nullptr,
+                                             ctx.geo_n0);
       ctx.coarse_A64.upload(A);
       std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
       std::vector<float> inv32(inv.begin(), inv.end());

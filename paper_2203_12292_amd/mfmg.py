@@ -45,7 +45,7 @@ class LevelDesc(C.Structure):
                 ("cheb_degree", C.c_int), ("smoothing_range", C.c_double), ("eig_safety", C.c_double),
                 ("eig_iterations", C.c_int), ("max_rhs", C.c_int), ("drop_coarse", C.c_int),
                 ("coef_kind", C.c_int), ("coef_params", C.c_double * 8), ("graph_vcycle", C.c_int),
-                ("fmg_start", C.c_int)]
+                ("fmg_start", C.c_int), ("geom_kind", C.c_int), ("geom_params", C.c_double * 8)]
 
 
 class NetTrainDesc(C.Structure):
@@ -255,7 +255,7 @@ class Solver:
 
     def __init__(self, mesh, degree, scheme=SCHEME_H, level_dtypes=None, dirichlet=True, cheb_degree=3,
                  max_rhs=1, smoothing_range=20.0, eig_safety=1.2, eig_iterations=15, drop_coarse=0,
-                 coef=None, graph_vcycle=False, fmg_start=False):
+                 coef=None, graph_vcycle=False, fmg_start=False, geometry=None):
         d = LevelDesc()
         d.degree, d.scheme, d.dirichlet = degree, scheme, int(dirichlet)
         level_dtypes = list(level_dtypes or [])
@@ -269,6 +269,10 @@ class Solver:
             d.coef_kind = coef["kind"]
             for i, v in enumerate(coef["params"]):
                 d.coef_params[i] = v
+        if geometry is not None:  # a synth geometry descriptor {"kind": k, "params": [...]}
+            d.geom_kind = geometry["kind"]
+            for i, v in enumerate(geometry["params"]):
+                d.geom_params[i] = v
         self.desc = d
         self.handle = C.c_void_p()
         self.mesh = mesh

@@ -66,6 +66,20 @@ COEF_INCLUSION = coef_desc(COEF_BALL, (0.5, 0.5, 0.5, 0.3, 1000.0, 1.0))
 # coarse grids of the benchmark meshes
 COEF_CHECKER_1000 = coef_desc(COEF_CHECKER, (1.0, 1000.0, 0.25, 0.0))
 
+# Cell-geometry descriptors (kinds as the library's geom_kind): the coarse-grid
+# vertices moved by an affine map (kind 1, parameters of an upper-triangular
+# matrix) or by an interior bump that keeps the boundary (kind 2, amplitude
+# and direction).  Parameters only, no arithmetic.
+GEOM_NONE, GEOM_AFFINE, GEOM_BUMP = 0, 1, 2
+
+
+def geom_desc(kind, params):
+    return {"kind": int(kind), "params": [float(p) for p in params]}
+
+
+GEOM_SHEAR = geom_desc(GEOM_AFFINE, (1.3, 0.4, -0.2, 0.9, 0.3, 1.1))
+GEOM_BUMP8 = geom_desc(GEOM_BUMP, (0.08, 1.0, -0.7, 0.5))
+
 
 def mesh_desc(name, n0, lo, hi, n_global, steps):
     return {"name": name, "n0": int(n0), "lo": float(lo), "hi": float(hi),
