@@ -406,7 +406,9 @@ def hanging_node_overhead(k=4, reps=20):
     from paper_2203_12292_amd import mfmg
     dev = torch.device("cuda:0")
     out = {}
-    for name, desc in (("uniform64", synth.mesh_desc("uniform64", 64, -1.0, 1.0, 0, [])),
+    # the uniform mesh comes from one cell by six global steps, as the paper's
+    # meshes do, so that its hierarchy has a small coarse grid
+    for name, desc in (("uniform64", synth.mesh_desc("uniform64", 1, -1.0, 1.0, 6, [])),
                        ("octant7", synth.octant_mesh(7)), ("shell8", synth.shell_mesh(8))):
         print(f"[bench] hanging-node overhead: {name}", file=sys.stderr, flush=True)
         mesh = mfmg.Mesh(desc)
@@ -430,6 +432,48 @@ def hanging_node_overhead(k=4, reps=20):
     return out
 
 
+def kernel_summary(trace_dir, pmc_dirs, title, commands, top=10):
+    """Markdown summary of a rocprofv3 run of one --profile workload: the
+    kernels by total time (dispatch count, median and mean duration) from
+    the kernel trace, and the mean of each counter per kernel from the --pmc
+    runs (the largest grid of each kernel name, i.e. the finest level)."""
+    import numpy as np
+    rows = []
+    for path in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                rows.append((_kname(r["Kernel_Name"]), grid,
+                             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    by = {}
+    for name, grid, us in rows:
+        by.setdefault((name, grid), []).append(us)
+    lines = [f"# {title}", "", "Commands:", ""] + [f"    {c}" for c in commands] + [""]
+    lines += ["| kernel | grid (threads) | dispatches | median us | mean us | total ms |", "|---|---|---|---|---|---|"]
+    for (name, grid), v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        lines.append(f"| `{name}` | {grid} | {len(v)} | {np.median(v):.1f} | {np.mean(v):.1f} | {sum(v) / 1e3:.2f} |")
+    for d in pmc_dirs:
+        vals = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path, newline="") as fh:
+                for r in csv.DictReader(fh):
+                    key = (_kname(r["Kernel_Name"]), int(r["Grid_Size"]))
+                    vals.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        best = {}
+        for (name, grid), cs in vals.items():
+            if name not in best or grid > best[name][0]:
+                best[name] = (grid, cs)
+        if not best:
+            continue
+        counters = sorted({c for _, cs in best.values() for c in cs})
+        lines += ["", f"Counters ({os.path.basename(d.rstrip('/'))}; mean per dispatch, largest grid of each kernel):", ""]
+        lines += ["| kernel | grid | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
+        for name, (grid, cs) in sorted(best.items(), key=lambda kv: -kv[1][0])[:top]:
+            lines.append(f"| `{name}` | {grid} | " +
+                         " | ".join(f"{np.mean(cs[c]):.4g}" if c in cs else "" for c in counters) + " |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,9 +487,15 @@ def main():
     ap.add_argument("--pmc-command", action="append", default=[], help="command lines to quote in the summary")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="print the kernel-trace summary of a profiled run and exit (no GPU)")
+    ap.add_argument("--kernel-summary", nargs="+", metavar="DIR",
+                    help="print a markdown summary of a kernel-trace folder and --pmc folders and exit (no GPU)")
+    ap.add_argument("--summary-title", default="rocprofv3 summary")
     ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
                     help="run only the kernels of one workload --steps times (for rocprofv3) and exit")
     args = ap.parse_args()
+    if args.kernel_summary:
+        print(kernel_summary(args.kernel_summary[0], args.kernel_summary[1:], args.summary_title, args.pmc_command))
+        return
     if args.profile:
         run_profile_workload(args.profile, args.steps, args.warmup)
         return
@@ -651,8 +701,11 @@ def main():
         solves["cube4_q2_ls_fp64"] = {"seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"],
                                       "residual": st["final_residual"]}
         del s1
-        # learned coarse correction (Q2 coarse grid, 343 DoFs)
-        s1 = mfmg.Solver(m1, 2, mfmg.SCHEME_H)
+        # learned coarse correction on a mesh whose coarse level matters:
+        # 6^3 coarse cubes (Q2 coarse problem of 1,331 DoFs, the network's
+        # size limit is 2,048), two uniform steps and one ball step
+        m5 = mfmg.Mesh(synth.CFG5_GAIN)
+        s1 = mfmg.Solver(m5, 2, mfmg.SCHEME_H)
         b1 = torch.zeros(s1.n_dofs(), dtype=torch.float64, device=dev)
         x1 = torch.zeros_like(b1)
         t0 = time.time()
@@ -670,11 +723,13 @@ def main():
         s1.net_record(0)
         g = synth.gaussian_rhs_training(100000)
         s1.rhs(b1, mfmg.RHS_GAUSS, g, n_terms=g.shape[0])
-        learned = {"pairs": 20000, "record_s": round(t_rec, 2), "train_s": round(t_train, 2),
+        learned = {"mesh": "cube6_g2_ball1", "free_dofs": s1.n_dofs(), "coarse_dofs": s1.n_dofs(0),
+                   "pairs": 20000, "record_s": round(t_rec, 2), "train_s": round(t_train, 2),
                    "train_loss_first_last": [hist[0], hist[-1]], "tau": 0.9}
-        for name, mode in (("exact", mfmg.COARSE_EXACT), ("learned", mfmg.COARSE_LEARNED),
-                           ("none", mfmg.COARSE_ZERO)):
-            s1.net_mode(mode, 0.9)
+        # network_alone: every prediction accepted (no exact fallback)
+        for name, mode, tau in (("exact", mfmg.COARSE_EXACT, 0.9), ("learned", mfmg.COARSE_LEARNED, 0.9),
+                                ("none", mfmg.COARSE_ZERO, 0.9), ("network_alone", mfmg.COARSE_LEARNED, 1e300)):
+            s1.net_mode(mode, tau)
             for _ in range(3):
                 if mode != mfmg.COARSE_EXACT:
                     s1.net_counts()
@@ -684,7 +739,7 @@ def main():
                 a, r, rel = s1.net_counts()
                 rec.update({"accepted": a, "rejected": r, "mean_rel_coarse_residual": rel})
             learned[name] = rec
-        solves["cube4_q2_learned_coarse"] = learned
+        solves["cube6_q2_learned_coarse"] = learned
         del s1
         # p-multigrid Q6 -> Q3 -> Q1 + global coarsening, 8 right-hand sides
         m4 = mfmg.Mesh(synth.CFG4)
@@ -697,6 +752,20 @@ def main():
         s4.rhs(b4, mfmg.RHS_GAUSS, params, n_terms=4, n_vec=8)
         x4 = torch.zeros_like(b4)
         st = s4.solve(x4, b4, rtol=1e-10, max_it=100, flexible=True, n_vec=8)
+        # the FP32 operator of the finest Q6 level on all 8 vectors at once
+        f4 = s4.n_levels - 1
+        x32 = torch.from_numpy(synth.uniform_vector(n4 * 8, seed=12292)).to(dev).float()
+        y32 = torch.empty_like(x32)
+        for _ in range(3):
+            s4.vmult(f4, y32, x32, n_vec=8)
+        ms4 = float(np.mean(_events_time(lambda: s4.vmult(f4, y32, x32, n_vec=8), 10, stream)))
+        alg4 = 8.0 * 8 * n4
+        out["roofline_q6_fp32_8vec"] = {
+            "bound": "hbm", "achieved": alg4 / (ms4 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "vmult_batch_kernel<6, float> + reduce_shared_kernel, 8 interleaved vectors",
+            "alg_bytes_per_launch": alg4, "avg_launch_ms": ms4, "dofs_per_s": 8 * n4 / (ms4 * 1e-3)}
+        del x32, y32
         solves["cube12_spheres_q6_pmg_8rhs_fp32_vcycle"] = {
             "seconds": st["time_ms"] * 1e-3, "iterations": st["iterations"], "residual": st["final_residual"],
             "free_dofs": n4, "n_rhs": 8, "levels": s4.n_levels, "setup_s": round(setup4, 2)}

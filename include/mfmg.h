@@ -379,6 +379,24 @@ int mfmg_distribute(mfmg_ctx ctx, int level, const void* x_f64, void* out_f64, v
  * (host arrays of n_cells and 3 n_cells entries). */
 int mfmg_level_cells(mfmg_ctx ctx, int level, int32_t* levels, int32_t* ijk);
 
+/* New diffusion coefficient, transferred to every multigrid level on the
+ * device (the interpolate_to_mg step of the transfer class, Section 3.5, for
+ * a field that is constant per cell; the operator -div(c grad u) of
+ * Eq. (impl:mf) with c in the quadrature-point term).  c_f64: device array of
+ * one value per cell of the finest level, in the order of
+ * mfmg_level_cells(ctx, n_levels - 1), each in [1e-30, 1e30] (else
+ * MFMG_ERR_INVALID_ARG and nothing changes).  Each coarser level's cell takes
+ * the value of the same cell on the next finer level or the mean of its
+ * eight children (summed in child order, x fastest), i.e. the average over
+ * the finest cells it covers, as at set-up; the operator uses it rounded to
+ * bfloat16.  The diagonals, the Chebyshev intervals (eigenvalue estimate
+ * repeated), the dense coarse inverse (reassembled on the host from the
+ * coarse level's cells) and the learned correction's residual check follow;
+ * V-cycles captured in graphs are dropped.  The network keeps its
+ * parameters.  Set-up call: allocates temporary device memory and
+ * synchronizes the stream.  Local-smoothing schemes: MFMG_ERR_UNSUPPORTED. */
+int mfmg_set_coefficient(mfmg_ctx ctx, const void* c_f64, void* stream);
+
 /* ---- learned coarse correction (an extension, not in the paper) ---------
  * A per-coarse-cell network replaces the exact coarse solve at level 0: input
  * the coarse right-hand side at the cell's (k+1)^3 nodes divided by

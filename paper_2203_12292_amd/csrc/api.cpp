@@ -621,6 +621,15 @@ int mfmg_net_train(mfmg_ctx ctx, const mfmg_net_train_desc* desc, float* history
   });
 }
 
+int mfmg_set_coefficient(mfmg_ctx ctx, const void* c_f64, void* stream) {
+  return guarded([&] {
+    check_ptr(ctx, "ctx");
+    check_vec(c_f64, ctx->ctx.levels.empty() ? 0 : ctx->ctx.levels.back().n_cells, "c");
+    mfmg::set_coefficient(ctx->ctx, static_cast<const double*>(c_f64), as_stream(stream));
+    return MFMG_OK;
+  });
+}
+
 int mfmg_net_infer(mfmg_ctx ctx, int dtype, void* y, const void* b, void* stream) {
   return guarded([&] {
     check_ptr(ctx, "ctx");

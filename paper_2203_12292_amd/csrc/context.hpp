@@ -87,8 +87,14 @@ struct GraphCache {
   GraphCache(const GraphCache&) = delete;
   GraphCache& operator=(const GraphCache&) = delete;
   ~GraphCache() {
-    for (auto& e : entries) (void)hipGraphExecDestroy(e.exec);
+    clear();
     if (capture) (void)hipStreamDestroy(capture);
+  }
+  // forget every captured cycle (their kernel arguments are out of date)
+  void clear() {
+    for (auto& e : entries) (void)hipGraphExecDestroy(e.exec);
+    entries.clear();
+    seen.clear();
   }
 };
 
@@ -109,8 +115,10 @@ struct Context {
   Level active;
   int max_rhs = 1;
   int cheb_degree = 3;
-  // exact coarse solver: dense inverse of A^(0)
+  // exact coarse solver: dense inverse of A^(0), and the host description of
+  // level 0 it is assembled from (kept to reassemble it)
   int64_t n0 = 0;
+  LevelDofs coarse_host;
   DeviceArray<double> coarse_inv64;
   DeviceArray<double> coarse_A64;
   NetState net;
@@ -148,5 +156,8 @@ void copy_to_mg(Context& ctx, int l, int nv, void* dst, const double* src, hipSt
 void copy_from_mg(Context& ctx, int l, int nv, double* dst, const void* src, hipStream_t s);
 int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_it, bool flexible,
         mfmg_solve_stats* stats, hipStream_t s);
+// new cellwise-constant coefficient from the finest level's cell values
+// (device array); synchronizes `s`
+void set_coefficient(Context& ctx, const double* c_fine, hipStream_t s);
 
 }  // namespace mfmg

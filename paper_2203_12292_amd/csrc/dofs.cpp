@@ -111,12 +111,7 @@ double cell_coef(const CoefDesc& cd, const Octree& fine, int l, int64_t i, int64
 
 uint32_t coef_mask_bits(double c) {
   MFMG_REQUIRE(c >= 1e-30 && c <= 1e30, MFMG_ERR_INVALID_ARG, "the coefficient must lie in [1e-30, 1e30]");
-  int e = 0;
-  const double m = std::frexp(c, &e);                       // c = m 2^e, 1/2 <= m < 1
-  const double q = std::nearbyint(std::ldexp(m, 8));        // 8 significant bits, ties to even
-  const float f = static_cast<float>(std::ldexp(q, e - 8));  // exact in float
-  const uint32_t b = __builtin_bit_cast(uint32_t, f);
-  return ((b >> 23) & 0xffu) << 24 | ((b >> 16) & 0x7fu) << 9;
+  return coef_bits(c);
 }
 
 LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_codes, int only_level,
@@ -531,7 +526,7 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
     std::sort(seen.begin(), seen.end());
     seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
     for (int32_t id : seen) {
-      MFMG_REQUIRE(count[id] < 255, MFMG_ERR_INVALID_ARG, "valence overflow");
+      MFMG_REQUIRE(count[id] < TRANSFER_OWNER - 1, MFMG_ERR_INVALID_ARG, "valence overflow");
       ++count[id];
     }
   }
@@ -540,9 +535,43 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
     for (int s = 0; s < N_SLOTS; ++s) {
       const int32_t id = fine.ent_id[s * nf + c];
       if (id < 0 || fine.slot_hanging(c, s)) continue;
-      MFMG_REQUIRE(count[id] > 0, MFMG_ERR_INVALID_ARG, "entity without a transfer group");
+      MFMG_REQUIRE(count[id] > 0 && count[id] < TRANSFER_OWNER, MFMG_ERR_INVALID_ARG,
+                   "entity without a transfer group, or valence overflow");
       T.valence[s * nf + c] = count[id];
     }
+  // owner: of the (fine cell, slot) pairs through which the transfer kernels
+  // reach an unconstrained entity, the first one (identity groups, then
+  // refinement groups, nodes in lattice order); every other pair skips it.
+  // A refinement group's lattice has 2k+1 nodes per axis, node I belonging
+  // to child I >= k (local node I - k), so an entity on a face between
+  // children is reached through one child only.
+  const int kf = fine.k;
+  std::vector<uint8_t> claimed(fine.n_entities, 0);
+  auto visit = [&](int64_t f, int a, int b, int c) {
+    const int s = node_slot(a, b, c, kf);
+    uint8_t& v = T.valence[s * nf + f];
+    if (v == 0) return;  // constrained or Dirichlet
+    const int32_t id = fine.ent_id[s * nf + f];
+    if (!claimed[id]) {
+      claimed[id] = 1;
+      v |= TRANSFER_OWNER;
+    }
+  };
+  for (size_t q = 0; q < T.ident_fine.size(); ++q)
+    for (int c = 0; c <= kf; ++c)
+      for (int b = 0; b <= kf; ++b)
+        for (int a = 0; a <= kf; ++a) visit(T.ident_fine[q], a, b, c);
+  const int64_t nr = static_cast<int64_t>(T.refined_coarse.size());
+  for (int64_t r = 0; r < nr; ++r)
+    for (int L = 0; L <= 2 * kf; ++L)
+      for (int J = 0; J <= 2 * kf; ++J)
+        for (int I = 0; I <= 2 * kf; ++I) {
+          const int cx = I >= kf, cy = J >= kf, cz = L >= kf;
+          visit(T.refined_fine[(cx + 2 * cy + 4 * cz) * nr + r], I - cx * kf, J - cy * kf, L - cz * kf);
+        }
+  for (int64_t e = 0; e < fine.n_entities; ++e)  // (entities without DoFs, e.g. edges at k = 1, need none)
+    MFMG_REQUIRE(count[e] == 0 || fine.ent_size[e] == 0 || claimed[e], MFMG_ERR_INVALID_ARG,
+                 "transfer entity without an owner");
   return T;
 }
 

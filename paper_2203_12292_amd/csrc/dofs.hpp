@@ -125,7 +125,11 @@ struct TransferDofs {
   std::vector<int32_t> ident_coarse, ident_fine;   // identity category pairs
   std::vector<int32_t> refined_coarse;             // refinement category coarse cells
   std::vector<int32_t> refined_fine;               // [8][n_refined] children, child c = sx + 2 sy + 4 sz
-  std::vector<uint8_t> valence;                    // [N_SLOTS][n_fine_cells]
+  // [N_SLOTS][n_fine_cells]: number of groups in which the entity appears
+  // unconstrained (0: constrained or Dirichlet), plus TRANSFER_OWNER on the
+  // one (fine cell, slot) pair that writes (prolongation) or reads
+  // (restriction) the entity
+  std::vector<uint8_t> valence;
 };
 
 // With skip_unrefined, coarse cells that are neither fine cells nor parents of

@@ -136,6 +136,29 @@ OpTab2<T, N> make_optab2() {
   return o;
 }
 
+// The hanging interpolation matrices of both halves in constant memory, for
+// wavefronts holding one cell: read with uniform addresses, they become
+// scalar loads and scalar operands.  Filled once per device before the first
+// operator launch that uses them.
+template <typename T, int N>
+struct HgTable {
+  T v[2 * N * N];
+};
+template <typename T, int N>
+__constant__ HgTable<T, N> kHgTab;
+
+template <typename T, int N>
+void ensure_hg_table() {
+  static bool done[64] = {};
+  int dev = 0;
+  MFMG_HIP(hipGetDevice(&dev));
+  MFMG_REQUIRE(dev >= 0 && dev < 64, MFMG_ERR_UNSUPPORTED, "device index");
+  if (done[dev]) return;
+  const OpTab2<T, N> o = make_optab2<T, N>();
+  MFMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL((kHgTab<T, N>)), o.Hg, sizeof(o.Hg)));
+  done[dev] = true;
+}
+
 // y = A x for a SymMat A (even-odd evaluation)
 template <int N, typename T>
 __device__ __forceinline__ void sym_mv(const SymMat<T, N>& A, const T (&x)[N], T (&y)[N]) {
@@ -182,6 +205,42 @@ __device__ __forceinline__ void interp_lds(const T* __restrict__ Hg, int s, T (&
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) u[i] = out[i];
+}
+
+// The same from the constant-memory table when s is the same on every lane
+// of the wavefront (one cell per wavefront): the branch is uniform and the
+// table entries are scalar operands, no LDS reads.
+template <int N, typename T, bool TRANS, int S>
+__device__ __forceinline__ void interp_const(T (&u)[N]) {
+  // an opaque copy of the table address keeps the loads here, next to their
+  // use (hoisted out of the cell loop, 2 x N^2 values would not fit the
+  // scalar registers)
+  using CT = const __attribute__((address_space(4))) T;
+  CT* tbl = reinterpret_cast<CT*>(reinterpret_cast<uintptr_t>(kHgTab<T, N>.v)) + S * N * N;
+  asm volatile("" : "+s"(tbl));
+  T out[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc += tbl[TRANS ? j * N + i : i * N + j] * u[j];
+    out[i] = acc;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = out[i];
+}
+
+// u <- H_s u (H_s^T u if TRANS) for the hanging lines of a cell; UNI: s is
+// wavefront-uniform and the matrices come from constant memory, otherwise
+// from their LDS copy Hg
+template <int N, typename T, bool TRANS, bool UNI>
+__device__ __forceinline__ void hang_interp(const T* __restrict__ Hg, int s, T (&u)[N]) {
+  if constexpr (UNI) {
+    if (s) interp_const<N, T, TRANS, 1>(u);
+    else interp_const<N, T, TRANS, 0>(u);
+  } else {
+    interp_lds<N, T, TRANS>(Hg, s, u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -406,9 +465,10 @@ __device__ __forceinline__ void cell_pipeline(T* __restrict__ B0, T* __restrict_
 // applied around the sweeps: z in registers and y, x through LDS before,
 // x in registers and y, z through LDS after; the result is then this lane's
 // z-line (the gather layout) and the function returns true.  Hg (LDS) holds
-// the interpolation matrices of both halves.  Must be called by all lanes of
-// the wavefront.
-template <int K, typename T, typename Sync>
+// the interpolation matrices of both halves.  UNI: the wavefront holds one
+// cell and m is wavefront-uniform (the interpolation then reads its matrices
+// from the kernel arguments).  Must be called by all lanes of the wavefront.
+template <int K, typename T, typename Sync, bool UNI = false>
 __device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, uint32_t m,
                                                      int any_hang, T h, const OpTab2<T, K + 1>& tab,
                                                      const T* __restrict__ Hg, int ta, int tb, T (&u)[K + 1]) {
@@ -416,14 +476,14 @@ __device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, uint32_
   const Sync sync{};
   const bool hang = mask_hanging(m);
   if (any_hang) {
-    if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, false>(Hg, mask_sub(m, 2), u);
+    if (hang && hanging_line(m, 2, ta, tb, K)) hang_interp<N, T, false, UNI>(Hg, mask_sub(m, 2), u);
 #pragma unroll
     for (int c = 0; c < N; ++c) B0[c * N2 + tb * N + ta] = u[c];
     sync();
     if (hang && hanging_line(m, 1, ta, tb, K)) {
 #pragma unroll
       for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
-      interp_lds<N, T, false>(Hg, mask_sub(m, 1), u);
+      hang_interp<N, T, false, UNI>(Hg, mask_sub(m, 1), u);
 #pragma unroll
       for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
     }
@@ -431,7 +491,7 @@ __device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, uint32_
     if (hang && hanging_line(m, 0, ta, tb, K)) {
 #pragma unroll
       for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + ta * N + r];
-      interp_lds<N, T, false>(Hg, mask_sub(m, 0), u);
+      hang_interp<N, T, false, UNI>(Hg, mask_sub(m, 0), u);
 #pragma unroll
       for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];
     }
@@ -482,21 +542,21 @@ __device__ __forceinline__ bool cell_pipeline_zfirst(T* __restrict__ B0, uint32_
 #pragma unroll
   for (int r = 0; r < N; ++r) u[r] = h * (c[r] + b[r]);
   if (!any_hang) return false;
-  if (hang && hanging_line(m, 0, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 0), u);
+  if (hang && hanging_line(m, 0, ta, tb, K)) hang_interp<N, T, true, UNI>(Hg, mask_sub(m, 0), u);
 #pragma unroll
   for (int r = 0; r < N; ++r) B0[tb * N2 + ta * N + r] = u[r];  // this lane's own x-line
   sync();
   if (hang && hanging_line(m, 1, ta, tb, K)) {
 #pragma unroll
     for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
-    interp_lds<N, T, true>(Hg, mask_sub(m, 1), u);
+    hang_interp<N, T, true, UNI>(Hg, mask_sub(m, 1), u);
 #pragma unroll
     for (int r = 0; r < N; ++r) B0[tb * N2 + r * N + ta] = u[r];
   }
   sync();
 #pragma unroll
   for (int c = 0; c < N; ++c) u[c] = B0[c * N2 + tb * N + ta];
-  if (hang && hanging_line(m, 2, ta, tb, K)) interp_lds<N, T, true>(Hg, mask_sub(m, 2), u);
+  if (hang && hanging_line(m, 2, ta, tb, K)) hang_interp<N, T, true, UNI>(Hg, mask_sub(m, 2), u);
   return true;
 }
 
@@ -916,8 +976,11 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
     for (; cw < c1; cw += BATCH_WAVES * CPW) {
       const Pre cur = nx;
       nx = fetch(cw + BATCH_WAVES * CPW + lc);
-      const uint32_t mk = cur.mask;
-      const int wave_hang = __any(mask_hanging(mk) ? 1 : 0);
+      // one cell per wavefront: its mask is uniform (lanes without a cell
+      // take it too; their results are discarded)
+      constexpr bool UNI = CPW == 1 && GEO == 0;
+      const uint32_t mk = UNI ? __builtin_amdgcn_readfirstlane(cur.mask) : cur.mask;
+      const int wave_hang = UNI ? (mask_hanging(mk) ? 1 : 0) : __any(mask_hanging(mk) ? 1 : 0);
       const T h = static_cast<T>(ldexp(h0, -mask_level(mk)) * static_cast<double>(mask_coef(mk)));
       T u[N];
       u[0] = in_[cur.g0 + go0];
@@ -932,7 +995,7 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
         const CellGeo<T> g = cell_geo<T>(geo, ijk, cell, mask_level(mk), n0);
         cell_pipeline_mapped<K, T, WaveSync>(B0, mk, wave_hang, static_cast<T>(mask_coef(mk)), mt, g, Hg, ta, tb, u);
       } else {
-        zline = cell_pipeline_zfirst<K, T, WaveSync>(B0, mk, wave_hang, h, tab, Hg, ta, tb, u);
+        zline = cell_pipeline_zfirst<K, T, WaveSync, UNI>(B0, mk, wave_hang, h, tab, Hg, ta, tb, u);
       }
       // scatter-add along the result line, skipping absent entities and
       // lanes without a cell (they point at the zero block); a line through
@@ -986,10 +1049,19 @@ __global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __
   }
 }
 
-// Diagonal (Eq. impl:mf:diagonal).  Cells without constraints: d_e(i) =
-// A_e(i,i) = h (K_aa M_bb M_cc + M_aa K_bb M_cc + M_aa M_bb K_cc).  Cells with
-// hanging nodes: apply C_e^T A_e C_e to every unit slot vector e_s and keep
-// entry s.  One cell per block, n^2 threads.
+// Does the hanging-node interpolation C_e touch node (a, b, c)?  Only if one
+// of the three lines through the node is interpolated: otherwise C_e e_s =
+// e_s for its slot s (the in-place line interpolations mix values along
+// their own lines only), and (C_e^T A_e C_e)_ss = A_e(s, s).
+__device__ __forceinline__ bool node_constrained(uint32_t m, int a, int b, int c, int k) {
+  return hanging_line(m, 0, b, c, k) || hanging_line(m, 1, a, c, k) || hanging_line(m, 2, a, b, k);
+}
+
+// Diagonal (Eq. impl:mf:diagonal).  d_e(i) = A_e(i,i) = h (K_aa M_bb M_cc +
+// M_aa K_bb M_cc + M_aa M_bb K_cc) for every node that the cell's hanging-node
+// interpolation leaves alone; for the others (the nodes of hanging faces and
+// edges) apply C_e^T A_e C_e to the unit slot vector e_s and keep entry s.
+// One cell per block, n^2 threads.
 template <int K>
 __global__ void __launch_bounds__((K + 1) * (K + 1))
     diag_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc, double h0,
@@ -1002,16 +1074,15 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   const uint32_t m = mask[cell];
   const double h = ldexp(h0, -mask_level(m)) * static_cast<double>(mask_coef(m));
   double d[N];  // y-line (x = ta, z = tb)
-  if (!mask_hanging(m)) {
 #pragma unroll
-    for (int r = 0; r < N; ++r)
-      d[r] = h * (tab.K[ta * N + ta] * tab.M[r * N + r] * tab.M[tb * N + tb] +
-                  tab.M[ta * N + ta] * tab.K[r * N + r] * tab.M[tb * N + tb] +
-                  tab.M[ta * N + ta] * tab.M[r * N + r] * tab.K[tb * N + tb]);
-  } else {
-    for (int r = 0; r < N; ++r) d[r] = 0.0;
+  for (int r = 0; r < N; ++r)
+    d[r] = h * (tab.K[ta * N + ta] * tab.M[r * N + r] * tab.M[tb * N + tb] +
+                tab.M[ta * N + ta] * tab.K[r * N + r] * tab.M[tb * N + tb] +
+                tab.M[ta * N + ta] * tab.M[r * N + r] * tab.K[tb * N + tb]);
+  if (mask_hanging(m)) {
     for (int s = 0; s < N3; ++s) {
       const int sa = s % N, sb = (s / N) % N, sc = s / N2;
+      if (!node_constrained(m, sa, sb, sc, K)) continue;  // uniform over the block
       double u[N];
 #pragma unroll
       for (int c = 0; c < N; ++c) u[c] = (ta == sa && tb == sb && c == sc) ? 1.0 : 0.0;
@@ -1019,7 +1090,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
       if (ta == sa && tb == sc) {
 #pragma unroll
         for (int r = 0; r < N; ++r)
-          if (r == sb) d[r] += u[r];
+          if (r == sb) d[r] = u[r];
       }
       WaveSync{}();
     }
@@ -1028,7 +1099,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
 }
 
 // scatter-add of the line of nodes (a, b, 0..k) (along z), as scatter_yline
-template <int K, typename T>
+template <int K, typename T, bool INTERIOR = true>
 __device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell, int a,
                                               int b, const T (&w)[K + 1], T* __restrict__ dst) {
   const int s0 = node_slot(a, b, 0, K), s1 = node_slot(a, b, K, K);
@@ -1041,7 +1112,7 @@ __device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, i
     const int om = node_offset(a, b, 1, K);
     const int st = K > 2 ? node_offset(a, b, 2, K) - om : 0;
     const int32_t em = ent[sm * nc + cell];
-    if (em >= 0) {
+    if (em >= 0 && (INTERIOR || sm != 26)) {
 #pragma unroll
       for (int c = 1; c < K; ++c) {
         if (sm == 26) dst[em + om + (c - 1) * st] = w[c];
@@ -1057,8 +1128,8 @@ __device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, i
 // two gradient components is a product of 1D factors, so the six symmetric
 // components of G contract with squared 1D tables (E = S.S, F = S'.S',
 // X = S'.S elementwise; S' = l'(g_q)) axis by axis: 6 x 3 sweeps.  One cell
-// per block of n^2 threads; cells with hanging nodes are left to
-// diag_mapped_kernel.
+// per block of n^2 threads.  In cells with hanging nodes the nodes that the
+// interpolation touches are left to diag_mapped_kernel (written as 0 here).
 template <typename T, int N>
 struct DiagTab {
   T E[N * N], F[N * N], X[N * N];  // [q][a]
@@ -1073,7 +1144,6 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   __shared__ double B[N3];
   const int64_t cell = blockIdx.x;
   const uint32_t m = mask[cell];
-  if (mask_hanging(m)) return;
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const CellGeo<double> g = cell_geo<double>(geo, ijk, cell, mask_level(m), n0);
   const double coef = static_cast<double>(mask_coef(m));
@@ -1122,12 +1192,19 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
 #pragma unroll
     for (int c = 0; c < N; ++c) d[c] += w[c];
   }
+  if (mask_hanging(m)) {
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+      if (node_constrained(m, ta, tb, c, K)) d[c] = 0.0;
+  }
   scatter_zline<K>(ent, nc, cell, ta, tb, d, diag);
 }
 
-// Diagonal of a mapped cell with hanging nodes (Eq. impl:mf:diagonal): the
-// cell operator C_e^T A_e C_e applied to every unit slot vector e_s, entry s
-// kept.  One cell per block of n^2 threads (one wavefront).
+// Diagonal of a mapped cell with hanging nodes (Eq. impl:mf:diagonal), the
+// nodes that the interpolation touches: the cell operator C_e^T A_e C_e
+// applied to the unit slot vector e_s, entry s kept (the other nodes come
+// from diag_mapped_direct_kernel; the cell interior is never touched and not
+// written here).  One cell per block of n^2 threads (one wavefront).
 template <int K>
 __global__ void __launch_bounds__((K + 1) * (K + 1))
     diag_mapped_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
@@ -1151,6 +1228,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
   for (int sc = 0; sc < N; ++sc)
     for (int sb = 0; sb < N; ++sb)
       for (int sa = 0; sa < N; ++sa) {
+        if (!node_constrained(m, sa, sb, sc, K)) continue;  // uniform over the block
         double u[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) u[c] = (ta == sa && tb == sb && c == sc) ? 1.0 : 0.0;
@@ -1162,7 +1240,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
         }
         WaveSync{}();
       }
-  scatter_zline<K>(ent, nc, cell, ta, tb, d, diag);
+  scatter_zline<K, double, false>(ent, nc, cell, ta, tb, d, diag);
 }
 
 // Constraint distribution: gather G_e and hanging-node interpolation C_e of
@@ -1325,8 +1403,13 @@ namespace mfmg {
 // cell (transfer group) per block.  Prolongation:
 //   coarse gather G_c with constraints C_c (in-place interpolation),
 //   category prolongation P (three 1D sweeps; identity category: none),
-//   weights W = 1/valence (0 for constrained fine DoFs), scatter S_f.
-// Restriction is the transpose of every step.
+//   weights W, scatter S_f.
+// Restriction is the transpose of every step.  The weights: the paper's W
+// divides each fine value by the number of groups that reach it, so that the
+// groups' equal contributions sum to it once.  Here W is 1 on one owner
+// (fine cell, slot) pair per fine entity and 0 elsewhere (and on constrained
+// fine DoFs): the same operator, and the prolongation writes each fine DoF
+// from one block with a plain read-modify-write instead of atomics.
 //
 // Lattice of a group: NF nodes per axis.  Refinement category: NF = 2k+1
 // nodes covering the 8 children (child along an axis = node index >= k);
@@ -1460,11 +1543,11 @@ __global__ void __launch_bounds__(TR_THREADS)
       const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
       const int64_t f = group_fine[child * ngroups + g];
       const int s = node_slot(a, b, c, KF);
-      const int val = valence[s * nfc + f];
-      if (val == 0) continue;
+      // one (cell, slot) pair owns each fine entity: a plain read-modify-write
+      if (!(valence[s * nfc + f] & TRANSFER_OWNER)) continue;
       const int32_t e = fent[s * nfc + f];
       const int64_t idx = static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v0 + vv;
-      add_to<S, T>(&dst[idx], Y[i * VB + vv] / static_cast<T>(val), val == 1);
+      add_to<S, T>(&dst[idx], Y[i * VB + vv], true);
     }
   }
 }
@@ -1500,12 +1583,10 @@ __global__ void __launch_bounds__(TR_THREADS)
       const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
       const int64_t f = group_fine[child * ngroups + g];
       const int s = node_slot(a, b, c, KF);
-      const int val = valence[s * nfc + f];
       T y = T(0);
-      if (val) {
+      if (valence[s * nfc + f] & TRANSFER_OWNER) {  // each fine value enters once
         const int32_t e = fent[s * nfc + f];
-        y = load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v0 + vv]) /
-            static_cast<T>(val);
+        y = load_as<T>(src[static_cast<int64_t>(e + node_offset(a, b, c, KF)) * nv + v0 + vv]);
       }
       Yw[i * VB + vv] = y;
     }
@@ -1758,6 +1839,7 @@ void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const Fused
   if (c.n_cells == 0) return;
   static const OpTab2<T, N> tab = make_optab2<T, N>();
   static const MapTab<T, N> mt = make_maptab<T, N>();
+  if constexpr (cells_per_wave(N) == 1 && GEO == 0) ensure_hg_table<T, N>();
   const T* geo = nullptr;
   if constexpr (GEO != 0) geo = static_cast<const T*>(sizeof(T) == 8 ? c.geo64 : c.geo32);
   // persistent blocks: as many as are resident on the device at once (a
@@ -2183,6 +2265,61 @@ void launch_acc_to_storage(int dtype, int64_t n, const void* acc, void* dst, hip
       break;
     default: throw Error(MFMG_ERR_UNSUPPORTED, "dtype");
   }
+  check_launch();
+}
+
+namespace {
+__global__ void coef_check_kernel(int64_t n, const double* __restrict__ c, int* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    if (!(c[i] >= 1e-30 && c[i] <= 1e30)) flag[0] = 1;
+}
+
+__global__ void coef_restrict_kernel(int64_t n_ident, const int32_t* __restrict__ ident_c,
+                                     const int32_t* __restrict__ ident_f, int64_t n_ref,
+                                     const int32_t* __restrict__ ref_c, const int32_t* __restrict__ ref_f,
+                                     const double* __restrict__ cf, double* __restrict__ cc) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_ident + n_ref;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (i < n_ident) {
+      cc[ident_c[i]] = cf[ident_f[i]];
+    } else {
+      const int64_t r = i - n_ident;
+      double sum = 0.0;
+      for (int ch = 0; ch < 8; ++ch) sum += cf[ref_f[ch * n_ref + r]];
+      cc[ref_c[r]] = sum / 8.0;
+    }
+  }
+}
+
+__global__ void coef_apply_kernel(int64_t n, const double* __restrict__ c, uint32_t* __restrict__ mask,
+                                  CellMeta* __restrict__ meta) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t m = (mask[i] & ~MASK_COEF_BITS) | coef_bits(c[i]);
+    mask[i] = m;
+    meta[i].mask = m;
+  }
+}
+}  // namespace
+
+void launch_coef_check(int64_t n, const double* c, int* flag, hipStream_t s) {
+  if (n == 0) return;
+  coef_check_kernel<<<grid_for(n), VEC_THREADS, 0, s>>>(n, c, flag);
+  check_launch();
+}
+
+void launch_coef_restrict(const TransferView& t, const double* c_fine, double* c_coarse, hipStream_t s) {
+  const int64_t n = t.n_ident + t.n_refined;
+  if (n == 0) return;
+  coef_restrict_kernel<<<grid_for(n), VEC_THREADS, 0, s>>>(t.n_ident, t.ident_coarse, t.ident_fine, t.n_refined,
+                                                         t.refined_coarse, t.refined_fine, c_fine, c_coarse);
+  check_launch();
+}
+
+void launch_coef_apply(int64_t n_cells, const double* c, uint32_t* mask, CellMeta* meta, hipStream_t s) {
+  if (n_cells == 0) return;
+  coef_apply_kernel<<<grid_for(n_cells), VEC_THREADS, 0, s>>>(n_cells, c, mask, meta);
   check_launch();
 }
 

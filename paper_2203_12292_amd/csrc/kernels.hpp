@@ -80,6 +80,17 @@ void launch_vmult(const CellView& c, int dtype, int nv, void* dst_acc, const voi
 // unused unless f.kind is FUSE_NONE)
 void launch_vmult_fused(const CellView& c, int dtype, int nv, void* dst_acc, const void* src, const FusedStep& f,
                         hipStream_t s);
+// Cellwise-constant coefficient on the levels (Section 3.5, interpolate_to_mg
+// for a cell field): flag[0] = 1 if a value of c[0..n) is outside
+// [1e-30, 1e30] or NaN (flag not cleared here)
+void launch_coef_check(int64_t n, const double* c, int* flag, hipStream_t s);
+// coarse-level cell values from the next finer level's: a coarse cell that
+// is also a fine cell takes its value, a refined one the mean of its eight
+// children (summed in child order, x fastest)
+void launch_coef_restrict(const TransferView& t, const double* c_fine, double* c_coarse, hipStream_t s);
+// write c (rounded to bfloat16) into the coefficient bits of the cell masks
+// and of the cells' operator records
+void launch_coef_apply(int64_t n_cells, const double* c, uint32_t* mask, CellMeta* meta, hipStream_t s);
 // diag (FP64) = diagonal of A
 void launch_diagonal(const CellView& c, double* diag, hipStream_t s);
 // b (FP64) += load vector; kind 0 const, 1 gaussians (params on device, n_terms per vector)

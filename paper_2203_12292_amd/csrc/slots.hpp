@@ -117,6 +117,24 @@ __host__ __device__ inline float mask_coef(uint32_t m) {
   const uint32_t bits = ((m >> 24) << 23) | (((m >> 9) & 0x7fu) << 16);
   return __builtin_bit_cast(float, bits);
 }
+constexpr uint32_t MASK_COEF_BITS = 0xff00fe00u;
+// transfer valence byte: owner flag (the low bits count the groups)
+constexpr uint8_t TRANSFER_OWNER = 0x80;
+// The mask bits of a coefficient c in [1e-30, 1e30]: c rounded to 8
+// significant bits (bfloat16), ties to even, from the bits of the double.
+__host__ __device__ inline uint32_t coef_bits(double c) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, c);
+  int e = static_cast<int>((b >> 52) & 0x7ff) - 1023 + 127;  // float exponent field
+  const uint64_t frac = b & ((uint64_t(1) << 52) - 1);
+  uint32_t m7 = static_cast<uint32_t>(frac >> 45);
+  const uint64_t rest = frac & ((uint64_t(1) << 45) - 1), half = uint64_t(1) << 44;
+  if (rest > half || (rest == half && (m7 & 1u))) ++m7;
+  if (m7 == 0x80u) {  // rounded up to the next power of two
+    m7 = 0;
+    ++e;
+  }
+  return static_cast<uint32_t>(e) << 24 | m7 << 9;
+}
 
 // Is the line along axis d through local node indices (p, q) of the other two
 // axes (in increasing axis order) interpolated by the hanging-node rule?

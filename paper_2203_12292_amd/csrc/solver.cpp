@@ -375,6 +375,19 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
 }
 }  // namespace
 
+namespace {
+// dense A^(0) of the coarse level (from its host description) and its inverse
+void setup_coarse_solver(Context& ctx) {
+  const LevelDofs& H = ctx.coarse_host;
+  std::vector<double> A = assemble_dense(H, Tables1D(H.k), ctx.geo.kind ? &ctx.geo_host : nullptr, ctx.geo_n0);
+  ctx.coarse_A64.upload(A);
+  std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
+  std::vector<float> inv32(inv.begin(), inv.end());
+  ctx.coarse_inv64.upload(inv);
+  ctx.coarse_inv32.upload(inv32);
+}
+}  // namespace
+
 void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc& desc, hipStream_t s) {
   MFMG_REQUIRE(desc.degree >= 1 && desc.degree <= 6, MFMG_ERR_UNSUPPORTED, "degree must be in [1, 6]");
   ctx.desc = desc;
@@ -447,19 +460,11 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
   sync(s);
   for (int l = 1; l < nl; ++l) estimate_eigenvalues(ctx, ctx.levels[l], eig_it, safety, range, s);
   // exact coarse solver
-  {
-    Level& L0 = ctx.levels[0];
-    ctx.n0 = L0.n_dofs;
-    if (desc.dirichlet) {  // (the pure Neumann coarse matrix is singular)
-      MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
-      std::vector<double> A = assemble_dense(host[0], Tables1D(L0.k), ctx.geo.kind ? &ctx.geo_host : nullptr,
-                                             ctx.geo_n0);
-      ctx.coarse_A64.upload(A);
-      std::vector<double> inv = spd_inverse(std::move(A), ctx.n0);
-      std::vector<float> inv32(inv.begin(), inv.end());
-      ctx.coarse_inv64.upload(inv);
-      ctx.coarse_inv32.upload(inv32);
-    }
+  ctx.n0 = ctx.levels[0].n_dofs;
+  if (desc.dirichlet) {  // (the pure Neumann coarse matrix is singular)
+    MFMG_REQUIRE(ctx.n0 <= 12000, MFMG_ERR_UNSUPPORTED, "coarse level too large for the dense direct solver");
+    ctx.coarse_host = host[0];
+    setup_coarse_solver(ctx);
   }
   // learned coarse correction (available for small coarse levels without hanging nodes)
   if (desc.dirichlet && ctx.n0 > 0 && ctx.n0 <= 2048 && host[0].n_hanging_cells == 0 && net_supported(host[0].k))
@@ -845,6 +850,56 @@ int pcg(Context& ctx, int nv, double* x, const double* b, double rtol, int max_i
     stats->time_ms = ms;
   }
   return status;
+}
+
+// The coefficient of every level from the finest level's cell values, on
+// the device (the transfer of a cell field to the multigrid levels, Section
+// 3.5): each coarser level's cells average the finer level's through the
+// transfer's cell groups; then the cell masks, the diagonals and inverse
+// diagonals, the Chebyshev intervals and the coarse direct solver follow the
+// new operator, and captured V-cycles are dropped.
+void set_coefficient(Context& ctx, const double* c_fine, hipStream_t s) {
+  MFMG_REQUIRE(!ctx.ls, MFMG_ERR_UNSUPPORTED, "the coefficient update is built for global-coarsening levels");
+  const int nl = static_cast<int>(ctx.levels.size());
+  const Level& F = ctx.levels.back();
+  {
+    DeviceArray<int> flag(1);
+    launch_fill(4, flag.ptr, 4, s);
+    launch_coef_check(F.n_cells, c_fine, flag.ptr, s);
+    int bad = 0;
+    MFMG_HIP(hipMemcpyAsync(&bad, flag.ptr, 4, hipMemcpyDeviceToHost, s));
+    sync(s);
+    MFMG_REQUIRE(bad == 0, MFMG_ERR_INVALID_ARG, "the coefficient must lie in [1e-30, 1e30]");
+  }
+  std::vector<DeviceArray<double>> val(nl);
+  const double* cur = c_fine;
+  for (int l = nl - 1; l >= 0; --l) {
+    Level& L = ctx.levels[l];
+    if (l < nl - 1) {
+      val[l].alloc(std::max<int64_t>(1, L.n_cells));
+      launch_coef_restrict(ctx.levels[l + 1].tview, cur, val[l].ptr, s);
+      cur = val[l].ptr;
+    }
+    launch_coef_apply(L.n_cells, cur, L.mask.ptr, L.meta.ptr, s);
+    launch_diagonal(L.view, L.diag.ptr, s);
+    launch_inverse_diag(MFMG_F64, L.n_dofs, L.diag.ptr, L.dinv.ptr, s);
+    launch_inverse_diag(MFMG_F32, L.n_dofs, L.diag.ptr, L.dinv.ptr + L.n_dofs * 8, s);
+  }
+  sync(s);
+  const mfmg_level_desc& desc = ctx.desc;
+  const double range = desc.smoothing_range > 0 ? desc.smoothing_range : 20.0;
+  const double safety = desc.eig_safety > 0 ? desc.eig_safety : 1.2;
+  const int eig_it = desc.eig_iterations > 0 ? desc.eig_iterations : 15;
+  for (int l = 1; l < nl; ++l) estimate_eigenvalues(ctx, ctx.levels[l], eig_it, safety, range, s);
+  if (desc.dirichlet) {
+    Level& L0 = ctx.levels[0];
+    MFMG_HIP(hipMemcpyAsync(ctx.coarse_host.mask.data(), L0.mask.ptr, L0.n_cells * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, s));
+    sync(s);
+    setup_coarse_solver(ctx);
+  }
+  ctx.graphs.clear();
+  sync(s);
 }
 
 }  // namespace mfmg

@@ -92,6 +92,7 @@ _SIGS = {
     "mfmg_rhs": (_I, [_P, _I, _I, C.POINTER(C.c_double), _I, _I, _P, _P]),
     "mfmg_distribute": (_I, [_P, _I, _P, _P, _P]),
     "mfmg_level_cells": (_I, [_P, _I, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "mfmg_set_coefficient": (_I, [_P, _P, _P]),
     "mfmg_net_n_params": (_I, [_P, C.POINTER(_I)]),
     "mfmg_net_record": (_I, [_P, _I]),
     "mfmg_net_n_recorded": (_I, [_P, C.POINTER(_I)]),
@@ -446,6 +447,15 @@ class Solver:
         _check(lib().mfmg_level_cells(self.handle, level, lv.ctypes.data_as(C.POINTER(C.c_int32)),
                                       ijk.ctypes.data_as(C.POINTER(C.c_int32))))
         return lv, ijk
+
+    def set_coefficient(self, c):
+        """New cellwise-constant diffusion coefficient from the finest level's
+        cell values (float64 device tensor in the order of level_cells of the
+        finest level); every level, diagonal, Chebyshev interval and the
+        coarse solver follow (a set-up call)."""
+        n = self.level_info(self.n_levels - 1)["n_cells"]
+        _vecs((c, n, "c", _f64("c"), None))
+        _check(lib().mfmg_set_coefficient(self.handle, _ptr(c), _stream()))
 
     # -- learned coarse correction ------------------------------------------------
     def net_n_params(self):

@@ -104,6 +104,11 @@ CFG2 = ball_mesh("cube16_ball4", 16, 0, 4)
 # by the spheres of radius 0.3 and 0.7 about the centre; Q6 -> Q3 -> Q1.
 CFG4 = mesh_desc("cube12_g1_spheres3", 12, -1.0, 1.0, 1,
                  [(SPHERE_CUT, (0.0, 0.0, 0.0, 0.3, 0.7))] * 3)
+# The learned coarse correction where the coarse level matters: 6^3 coarse
+# cubes (the Q2 coarse problem has 1,331 DoFs), two uniform steps and one
+# ball step; three levels, so the coarse correction carries the smooth error
+# that the smoothers of the two finer levels leave.
+CFG5_GAIN = ball_mesh("cube6_g2_ball1", 6, 2, 1)
 
 
 def octant_mesh(L):

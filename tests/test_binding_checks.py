@@ -65,3 +65,14 @@ def test_bad_vectors_raise_before_the_library(solver):
         S.coarse_solve(f64(10), f64(10))
     with pytest.raises(ValueError, match="elements"):
         S.net_infer(f64(10), f64(9))
+
+
+def test_set_coefficient_checks(solver):
+    S = solver
+    S.level_info = lambda level: {"n_cells": 7}
+    with pytest.raises(ValueError, match="elements"):
+        S.set_coefficient(torch.ones(8, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        S.set_coefficient(torch.ones(7, dtype=torch.float32))
+    with pytest.raises(ValueError, match="GPU"):
+        S.set_coefficient(torch.ones(7, dtype=torch.float64))

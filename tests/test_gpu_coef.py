@@ -106,3 +106,72 @@ def test_vcycle_and_solve(name, k, scheme, coef):
     err = np.linalg.norm(from_gpu(xs, PA) - xo) / np.linalg.norm(xo)
     print(f"[solve] {name} k={k} {scheme} {coef}: {st['iterations']} it, err {err:.2e}", flush=True)
     assert st["converged"] and err < 1e-10
+
+
+def fine_cell_values(S, space):
+    """The coefficient of the finest level's cells in the library's cell
+    order: the oracle's cell value (a leaf of the finest mesh takes c at its
+    centre)."""
+    lv, ijk = S.level_cells(S.n_levels - 1)
+    vals = [space.coef.raw((int(l), int(i), int(j), int(m))) for l, (i, j, m) in zip(lv, ijk)]
+    return torch.tensor(vals, dtype=torch.float64, device=DEV)
+
+
+def check_against(H, S, P, tag):
+    """Operator and diagonal of every level, the V-cycle (the library's
+    Chebyshev intervals given to the oracle) and a solve against the FP64
+    oracle of hierarchy H."""
+    rng = np.random.default_rng(5)
+    for l, L in enumerate(H.levels):
+        x = rng.uniform(-1, 1, L.A.shape[0])
+        y = torch.empty(L.A.shape[0], dtype=torch.float64, device=DEV)
+        S.vmult(l, y, to_gpu(x, P[l]))
+        d = torch.empty_like(y)
+        S.diagonal(l, d)
+        torch.cuda.synchronize()
+        assert rel_err(from_gpu(y, P[l]), L.A @ x) < 1e-12, (tag, l)
+        assert rel_err(from_gpu(d, P[l]), L.A.diagonal()) < 1e-12, (tag, l)
+    for l in range(1, S.n_levels):
+        H.levels[l].lmin, H.levels[l].lmax = S.smoother_range(l)
+    b = rng.uniform(-1, 1, H.fine.A.shape[0])
+    for rep in range(2):  # the second replays a captured cycle
+        xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+        bg = to_gpu(b, P[-1])
+        xs = torch.zeros_like(bg)
+        st = S.solve(xs, bg, rtol=1e-12, max_it=100)
+        torch.cuda.synchronize()
+        xo = solvers.direct_solve(H.fine.A, b)
+        err = np.linalg.norm(from_gpu(xs, P[-1]) - xo) / np.linalg.norm(xo)
+        assert st["converged"] and err < 1e-10, (tag, rep, err)
+    S.vcycle(xg, bg)
+    torch.cuda.synchronize()
+    assert rel_err(from_gpu(xg, P[-1]), H.vcycle(b)) < 1e-11, tag
+    return st["iterations"]
+
+
+@pytest.mark.parametrize("name,k,scheme", [("small", 2, "h"), ("small", 4, "h_then_p"), ("cfg1", 2, "h"),
+                                           ("spheres_small", 3, "hp")])
+def test_set_coefficient(name, k, scheme):
+    """mfmg_set_coefficient on a solver set up with c = 1: the coefficient
+    given on the finest cells reaches every level on the device, and every
+    level's operator and diagonal, the V-cycle and a solve then match the FP64
+    oracle set up with that coefficient; twice in a row (an inclusion, then a
+    checkerboard), the solver replaying graph-captured V-cycles.  Values out
+    of range are rejected and change nothing."""
+    from paper_2203_12292_amd import mfmg
+    print(f"[setup] set_coefficient mesh={name} k={k} scheme={scheme}", flush=True)
+    S = mfmg.Solver(mfmg.Mesh(DESCS[name]), k, SCHEME_CODES[scheme], graph_vcycle=True)
+    tree = oracle_tree(name)
+    H0 = Hierarchy(tree, k, scheme)
+    P = [perm_from_codes(V.codes_array(), S.dof_codes(l)) for l, V in enumerate(H0.spaces)]
+    check_against(H0, S, P, "c = 1")
+    for coef in ("inclusion", "checker"):
+        H = Hierarchy(tree, k, scheme, coef=COEFS[coef])
+        S.set_coefficient(fine_cell_values(S, H.spaces[-1]))
+        its = check_against(H, S, P, coef)
+        print(f"[set_coefficient] {name} k={k} {scheme} {coef}: {its} iterations", flush=True)
+    bad = fine_cell_values(S, H.spaces[-1])
+    bad[len(bad) // 2] = -1.0
+    with pytest.raises(mfmg.MfmgError):
+        S.set_coefficient(bad)
+    check_against(H, S, P, "after a rejected update")
