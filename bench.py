@@ -346,6 +346,9 @@ PROFILE_WORKLOADS = {
     "q6_f32x8_transfer": ("CFG4", 6, "p_then_h", "f32", 8, "transfer"),
     "q6_f32x8_smooth": ("CFG4", 6, "p_then_h", "f32", 8, "smooth"),
     "q4_f64_smooth": ("CFG2", 4, "h_then_p", "f64", 1, "smooth"),
+    "q4_f64_vmult_uniform64": ("UNIFORM64", 4, "h", "f64", 1, "vmult"),
+    "q4_f64_vmult_octant7": ("OCTANT7", 4, "h", "f64", 1, "vmult"),
+    "q4_f64_vmult_shell8": ("SHELL8", 4, "h", "f64", 1, "vmult"),
 }
 
 
@@ -408,8 +411,7 @@ def hanging_node_overhead(k=4, reps=20):
     out = {}
     # the uniform mesh comes from one cell by six global steps, as the paper's
     # meshes do, so that its hierarchy has a small coarse grid
-    for name, desc in (("uniform64", synth.mesh_desc("uniform64", 1, -1.0, 1.0, 6, [])),
-                       ("octant7", synth.octant_mesh(7)), ("shell8", synth.shell_mesh(8))):
+    for name, desc in (("uniform64", synth.UNIFORM64), ("octant7", synth.OCTANT7), ("shell8", synth.SHELL8)):
         print(f"[bench] hanging-node overhead: {name}", file=sys.stderr, flush=True)
         mesh = mfmg.Mesh(desc)
         cells, nh = mesh.info()
@@ -430,6 +432,37 @@ def hanging_node_overhead(k=4, reps=20):
     for name in ("octant7", "shell8"):
         out[name]["overhead_vs_uniform"] = out[name]["ns_per_dof"] / base - 1.0
     return out
+
+
+def ls_sweep():
+    """Iterations of global coarsening against local smoothing on the paper's
+    octant and shell meshes (L = 6, Q4) and the config-1 mesh (Q2) under
+    several Chebyshev settings (degree, smoothing range, Lanczos steps and
+    safety factor of the eigenvalue estimate); one JSON line per solve."""
+    import torch
+
+    import synth
+    from paper_2203_12292_amd import mfmg
+    dev = torch.device("cuda:0")
+    settings = ((3, 20.0, 15, 1.2), (3, 20.0, 60, 1.2), (3, 20.0, 15, 1.5), (3, 10.0, 15, 1.2),
+                (3, 30.0, 15, 1.2), (5, 20.0, 15, 1.2), (6, 20.0, 15, 1.2))
+    for mname, desc, k in (("octant6", synth.octant_mesh(6), 4), ("shell6", synth.shell_mesh(6), 4),
+                           ("cube4_g1_ball2", synth.CFG1, 2)):
+        mesh = mfmg.Mesh(desc)
+        for sch_name, sch in (("gc", mfmg.SCHEME_H), ("ls", mfmg.SCHEME_LS)):
+            for deg, rng, eit, saf in settings:
+                S = mfmg.Solver(mesh, k, sch, cheb_degree=deg, smoothing_range=rng, eig_iterations=eit,
+                                eig_safety=saf)
+                b = torch.zeros(S.n_dofs(), dtype=torch.float64, device=dev)
+                S.rhs(b)
+                x = torch.zeros_like(b)
+                st = S.solve(x, b, rtol=1e-10, max_it=100)
+                print(json.dumps({"mesh": mname, "degree": k, "scheme": sch_name, "cheb_degree": deg,
+                                  "smoothing_range": rng, "eig_iterations": eit, "eig_safety": saf,
+                                  "iterations": st["iterations"],
+                                  "lambda_max": [S.smoother_range(l)[1] for l in range(1, S.n_levels)]}),
+                      flush=True)
+                del S
 
 
 def kernel_summary(trace_dir, pmc_dirs, title, commands, top=10):
@@ -487,12 +520,17 @@ def main():
     ap.add_argument("--pmc-command", action="append", default=[], help="command lines to quote in the summary")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="print the kernel-trace summary of a profiled run and exit (no GPU)")
+    ap.add_argument("--ls-sweep", action="store_true",
+                    help="GC against LS iterations under several smoother settings (GPU), then exit")
     ap.add_argument("--kernel-summary", nargs="+", metavar="DIR",
                     help="print a markdown summary of a kernel-trace folder and --pmc folders and exit (no GPU)")
     ap.add_argument("--summary-title", default="rocprofv3 summary")
     ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
                     help="run only the kernels of one workload --steps times (for rocprofv3) and exit")
     args = ap.parse_args()
+    if args.ls_sweep:
+        ls_sweep()
+        return
     if args.kernel_summary:
         print(kernel_summary(args.kernel_summary[0], args.kernel_summary[1:], args.summary_title, args.pmc_command))
         return

@@ -35,6 +35,10 @@ struct Level {
   double lmin = 0.0, lmax = 1.0;
   // work vectors (max_rhs interleaved): storage type and arithmetic type
   DeviceArray<char> x, b, r, d, t, tmp_cast;
+  // deterministic mode: the level's cells colour by colour (diagonal, load
+  // vector) and the colour ranges of the transfer groups (restriction)
+  DeviceArray<int32_t> color_cells;
+  std::vector<int64_t> color_off, tr_ident_off, tr_refined_off;
   // transfer from level l-1 (fine side = this level)
   bool has_transfer = false;
   DeviceArray<int32_t> tr_ident_c, tr_ident_f, tr_ref_c, tr_ref_f;

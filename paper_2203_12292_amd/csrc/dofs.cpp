@@ -445,7 +445,56 @@ LevelDofs build_level_dofs(const Octree& tree, int k, bool dirichlet, bool want_
   return L;
 }
 
-TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial, bool skip_unrefined) {
+namespace {
+// Greedy colouring of n items, each touching the entities that ents_of lists
+// (slot 26, the cell interior, is never shared and not listed): an item takes
+// the lowest colour none of its entities has seen.  Returns the items in
+// colour order (stable) and the colour ranges.
+template <typename EntsOf>
+void greedy_colours(int64_t n, int64_t n_entities, EntsOf ents_of, std::vector<int64_t>& order,
+                    std::vector<int64_t>& off) {
+  std::vector<uint64_t> used(static_cast<size_t>(n_entities), 0);
+  std::vector<int8_t> colour(static_cast<size_t>(n));
+  int32_t ids[26];
+  int n_colours = 0;
+  for (int64_t q = 0; q < n; ++q) {
+    const int m = ents_of(q, ids);
+    uint64_t forbidden = 0;
+    for (int i = 0; i < m; ++i) forbidden |= used[ids[i]];
+    MFMG_REQUIRE(forbidden != ~uint64_t(0), MFMG_ERR_UNSUPPORTED, "deterministic mode: more than 64 colours");
+    const int c = __builtin_ctzll(~forbidden);
+    for (int i = 0; i < m; ++i) used[ids[i]] |= uint64_t(1) << c;
+    colour[q] = static_cast<int8_t>(c);
+    n_colours = std::max(n_colours, c + 1);
+  }
+  off.assign(n_colours + 1, 0);
+  for (int64_t q = 0; q < n; ++q) ++off[colour[q] + 1];
+  for (int c = 0; c < n_colours; ++c) off[c + 1] += off[c];
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  order.assign(n, 0);
+  for (int64_t q = 0; q < n; ++q) order[pos[colour[q]]++] = q;
+}
+
+// the entities (slots 0..25, Dirichlet left out) of cell c of level L
+int cell_entities(const LevelDofs& L, int64_t c, int32_t* ids) {
+  int m = 0;
+  for (int s = 0; s < 26; ++s) {
+    const int32_t id = L.ent_id[s * L.n_cells + c];
+    if (id >= 0) ids[m++] = id;
+  }
+  return m;
+}
+}  // namespace
+
+void colour_cells(const LevelDofs& L, std::vector<int32_t>& cells, std::vector<int64_t>& off) {
+  std::vector<int64_t> order;
+  greedy_colours(L.n_cells, L.n_entities, [&](int64_t c, int32_t* ids) { return cell_entities(L, c, ids); }, order,
+                 off);
+  cells.assign(order.begin(), order.end());
+}
+
+TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial, bool skip_unrefined,
+                            bool coloured) {
   TransferDofs T;
   T.polynomial = polynomial;
   const int64_t nf = fine.n_cells, ncc = coarse.n_cells;
@@ -539,6 +588,24 @@ TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool
                    "entity without a transfer group, or valence overflow");
       T.valence[s * nf + c] = count[id];
     }
+  if (coloured) {  // group lists in colour order (the restriction's coarse entities)
+    std::vector<int64_t> order;
+    const std::vector<int32_t> ic = T.ident_coarse, jf = T.ident_fine;
+    greedy_colours(static_cast<int64_t>(ic.size()), coarse.n_entities,
+                   [&](int64_t q, int32_t* ids) { return cell_entities(coarse, ic[q], ids); }, order, T.ident_off);
+    for (size_t q = 0; q < order.size(); ++q) {
+      T.ident_coarse[q] = ic[order[q]];
+      T.ident_fine[q] = jf[order[q]];
+    }
+    const int64_t nrg = static_cast<int64_t>(T.refined_coarse.size());
+    const std::vector<int32_t> rc = T.refined_coarse, rf = T.refined_fine;
+    greedy_colours(nrg, coarse.n_entities, [&](int64_t q, int32_t* ids) { return cell_entities(coarse, rc[q], ids); },
+                   order, T.refined_off);
+    for (int64_t q = 0; q < nrg; ++q) {
+      T.refined_coarse[q] = rc[order[q]];
+      for (int ch = 0; ch < 8; ++ch) T.refined_fine[ch * nrg + q] = rf[ch * nrg + order[q]];
+    }
+  }
   // owner: of the (fine cell, slot) pairs through which the transfer kernels
   // reach an unconstrained entity, the first one (identity groups, then
   // refinement groups, nodes in lattice order); every other pair skips it.

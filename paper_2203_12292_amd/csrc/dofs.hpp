@@ -130,13 +130,21 @@ struct TransferDofs {
   // one (fine cell, slot) pair that writes (prolongation) or reads
   // (restriction) the entity
   std::vector<uint8_t> valence;
+  // with `coloured`: both group lists in colour order (no two groups of a
+  // colour share a coarse entity) and the colour ranges
+  std::vector<int64_t> ident_off, refined_off;
 };
 
 // With skip_unrefined, coarse cells that are neither fine cells nor parents of
 // fine cells are left out (local-smoothing levels: the active coarse cells
 // take no part in the transfer).
 TransferDofs build_transfer(const LevelDofs& fine, const LevelDofs& coarse, bool polynomial,
-                            bool skip_unrefined = false);
+                            bool skip_unrefined = false, bool coloured = false);
+
+// Cells of a level colour by colour, so that no two cells of a colour share
+// an entity outside their interiors (greedy in cell order, at most 64
+// colours): cells[] and the colour ranges off[] (n_colours + 1).
+void colour_cells(const LevelDofs& L, std::vector<int32_t>& cells, std::vector<int64_t>& off);
 
 // Copy between the active mesh and a local-smoothing level (Algorithm 1):
 // the interior (non-edge) entities of the level's leaves are entities of the

@@ -323,15 +323,23 @@ __device__ __forceinline__ void add_to(S* p, T v, bool exclusive) {
 
 // scatter-add of the line of nodes (a, 0..k, c) (along y); cell interiors are
 // owned by the cell (plain store), shared entities use atomics.
+// `plain`: no other cell writes the same entities concurrently (deterministic
+// mode, colour by colour), a plain read-modify-write.
+template <typename T>
+__device__ __forceinline__ void scatter_add(T* p, T v, bool plain) {
+  if (plain) *p += v;
+  else atomic_add(p, v);
+}
+
 template <int K, typename T>
 __device__ __forceinline__ void scatter_yline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell,
                                               int a, int c, const T (&w)[K + 1], T* __restrict__ dst, int nv,
-                                              int v) {
+                                              int v, bool plain = false) {
   const int s0 = node_slot(a, 0, c, K), s1 = node_slot(a, K, c, K);
   const int o0 = node_offset(a, 0, c, K);
   const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
-  if (e0 >= 0) atomic_add(&dst[static_cast<int64_t>(e0 + o0) * nv + v], w[0]);
-  if (e1 >= 0) atomic_add(&dst[static_cast<int64_t>(e1 + o0) * nv + v], w[K]);
+  if (e0 >= 0) scatter_add(&dst[static_cast<int64_t>(e0 + o0) * nv + v], w[0], plain);
+  if (e1 >= 0) scatter_add(&dst[static_cast<int64_t>(e1 + o0) * nv + v], w[K], plain);
   if constexpr (K > 1) {
     const int sm = node_slot(a, 1, c, K);
     const int om = node_offset(a, 1, c, K);
@@ -343,7 +351,8 @@ __device__ __forceinline__ void scatter_yline(const int32_t* __restrict__ ent, i
         for (int b = 1; b < K; ++b) dst[static_cast<int64_t>(em + om + (b - 1) * st) * nv + v] = w[b];
       } else {
 #pragma unroll
-        for (int b = 1; b < K; ++b) atomic_add(&dst[static_cast<int64_t>(em + om + (b - 1) * st) * nv + v], w[b]);
+        for (int b = 1; b < K; ++b)
+          scatter_add(&dst[static_cast<int64_t>(em + om + (b - 1) * st) * nv + v], w[b], plain);
       }
     }
   }
@@ -870,7 +879,7 @@ struct BatchWavesPerEu {
   static constexpr int value = GEO ? 2 : 4;
 };
 
-template <int K, typename S, typename T, int FK, int GEO>
+template <int K, typename S, typename T, int FK, int GEO, bool DET>
 __global__ void __launch_bounds__(BATCH_WAVES * 64)
     __attribute__((amdgpu_waves_per_eu(BatchWavesPerEu<K, FK, GEO>::value)))
     vmult_batch_kernel(const CellMeta* __restrict__ meta, const int32_t* __restrict__ bcell,
@@ -973,7 +982,16 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
     if constexpr (META_LDS) __syncthreads();
     Pre nx = fetch(cw + lc);
     if constexpr (!META_LDS) __syncthreads();
-    for (; cw < c1; cw += BATCH_WAVES * CPW) {
+    // deterministic mode: every wavefront runs the same number of rounds (the
+    // last one partly without cells), and the scatter below goes one cell at
+    // a time in cell order
+    const int rounds = DET ? (c1 - c0 + BATCH_WAVES * CPW - 1) / (BATCH_WAVES * CPW) : 0;
+    for (int round = 0;; ++round, cw += BATCH_WAVES * CPW) {
+      if constexpr (DET) {
+        if (round >= rounds) break;
+      } else {
+        if (cw >= c1) break;
+      }
       const Pre cur = nx;
       nx = fetch(cw + BATCH_WAVES * CPW + lc);
       // one cell per wavefront: its mask is uniform (lanes without a cell
@@ -1002,18 +1020,32 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       // the cell interior (slot 26) holds DoFs of this cell only
       const int s0 = zline ? cur.g0 : cur.s0, s1 = zline ? cur.g1 : cur.s1, sm = zline ? cur.gm : cur.sm;
       const int o0 = zline ? go0 : so0, om = zline ? gom : som, st = zline ? gst : sst;
-      if (s0 < ZB) atomicAdd(&out_[s0 + o0], static_cast<double>(u[0]));
-      if (s1 < ZB) atomicAdd(&out_[s1 + o0], static_cast<double>(u[K]));
-      if constexpr (K > 1) {
-        if (sm < ZB) {
-          if ((zline ? gsm : ssm) == 26) {
+      auto add = [&](int i, T v) {
+        if constexpr (DET) out_[i] += static_cast<double>(v);  // the only writer at this moment
+        else atomicAdd(&out_[i], static_cast<double>(v));
+      };
+      auto scatter = [&]() {
+        if (s0 < ZB) add(s0 + o0, u[0]);
+        if (s1 < ZB) add(s1 + o0, u[K]);
+        if constexpr (K > 1) {
+          if (sm < ZB) {
+            if ((zline ? gsm : ssm) == 26) {
 #pragma unroll
-            for (int r = 1; r < K; ++r) out_[sm + om + (r - 1) * st] = static_cast<double>(u[r]);
-          } else {
+              for (int r = 1; r < K; ++r) out_[sm + om + (r - 1) * st] = static_cast<double>(u[r]);
+            } else {
 #pragma unroll
-            for (int r = 1; r < K; ++r) atomicAdd(&out_[sm + om + (r - 1) * st], static_cast<double>(u[r]));
+              for (int r = 1; r < K; ++r) add(sm + om + (r - 1) * st, u[r]);
+            }
           }
         }
+      };
+      if constexpr (DET) {
+        for (int q = 0; q < BATCH_WAVES * CPW; ++q) {  // cell c0 + round * (block's cells) + q
+          if (lane_used && wave * CPW + lc == q) scatter();
+          __syncthreads();
+        }
+      } else {
+        scatter();
       }
       WaveSync{}();  // the next cell group reuses this wavefront's buffers
     }
@@ -1065,11 +1097,11 @@ __device__ __forceinline__ bool node_constrained(uint32_t m, int a, int b, int c
 template <int K>
 __global__ void __launch_bounds__((K + 1) * (K + 1))
     diag_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc, double h0,
-                OpTab<double, K + 1> tab, double* __restrict__ diag) {
+                OpTab<double, K + 1> tab, double* __restrict__ diag, const int32_t* __restrict__ cells) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
   __shared__ double B0[N3];
   __shared__ double B1[N3];
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = cells ? cells[blockIdx.x] : blockIdx.x;  // cells: one colour (deterministic mode)
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const uint32_t m = mask[cell];
   const double h = ldexp(h0, -mask_level(m)) * static_cast<double>(mask_coef(m));
@@ -1095,18 +1127,18 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
       WaveSync{}();
     }
   }
-  scatter_yline<K>(ent, nc, cell, ta, tb, d, diag, 1, 0);
+  scatter_yline<K>(ent, nc, cell, ta, tb, d, diag, 1, 0, cells != nullptr);
 }
 
 // scatter-add of the line of nodes (a, b, 0..k) (along z), as scatter_yline
 template <int K, typename T, bool INTERIOR = true>
 __device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, int64_t nc, int64_t cell, int a,
-                                              int b, const T (&w)[K + 1], T* __restrict__ dst) {
+                                              int b, const T (&w)[K + 1], T* __restrict__ dst, bool plain = false) {
   const int s0 = node_slot(a, b, 0, K), s1 = node_slot(a, b, K, K);
   const int o0 = node_offset(a, b, 0, K);
   const int32_t e0 = ent[s0 * nc + cell], e1 = ent[s1 * nc + cell];
-  if (e0 >= 0) atomic_add(&dst[e0 + o0], w[0]);
-  if (e1 >= 0) atomic_add(&dst[e1 + o0], w[K]);
+  if (e0 >= 0) scatter_add(&dst[e0 + o0], w[0], plain);
+  if (e1 >= 0) scatter_add(&dst[e1 + o0], w[K], plain);
   if constexpr (K > 1) {
     const int sm = node_slot(a, b, 1, K);
     const int om = node_offset(a, b, 1, K);
@@ -1116,7 +1148,7 @@ __device__ __forceinline__ void scatter_zline(const int32_t* __restrict__ ent, i
 #pragma unroll
       for (int c = 1; c < K; ++c) {
         if (sm == 26) dst[em + om + (c - 1) * st] = w[c];
-        else atomic_add(&dst[em + om + (c - 1) * st], w[c]);
+        else scatter_add(&dst[em + om + (c - 1) * st], w[c], plain);
       }
     }
   }
@@ -1139,10 +1171,11 @@ template <int K>
 __global__ void __launch_bounds__((K + 1) * (K + 1))
     diag_mapped_direct_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
                               const double* __restrict__ geo, const int32_t* __restrict__ ijk, int n0,
-                              MapTab<double, K + 1> mt, DiagTab<double, K + 1> dt, double* __restrict__ diag) {
+                              MapTab<double, K + 1> mt, DiagTab<double, K + 1> dt, double* __restrict__ diag,
+                              const int32_t* __restrict__ cells) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
   __shared__ double B[N3];
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = cells ? cells[blockIdx.x] : blockIdx.x;
   const uint32_t m = mask[cell];
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const CellGeo<double> g = cell_geo<double>(geo, ijk, cell, mask_level(m), n0);
@@ -1197,7 +1230,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
     for (int c = 0; c < N; ++c)
       if (node_constrained(m, ta, tb, c, K)) d[c] = 0.0;
   }
-  scatter_zline<K>(ent, nc, cell, ta, tb, d, diag);
+  scatter_zline<K>(ent, nc, cell, ta, tb, d, diag, cells != nullptr);
 }
 
 // Diagonal of a mapped cell with hanging nodes (Eq. impl:mf:diagonal), the
@@ -1209,13 +1242,14 @@ template <int K>
 __global__ void __launch_bounds__((K + 1) * (K + 1))
     diag_mapped_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask, int64_t nc,
                        const double* __restrict__ geo, const int32_t* __restrict__ ijk, int n0,
-                       MapTab<double, K + 1> mt, OpTab2<double, K + 1> tab, double* __restrict__ diag) {
+                       MapTab<double, K + 1> mt, OpTab2<double, K + 1> tab, double* __restrict__ diag,
+                       const int32_t* __restrict__ cells) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
   __shared__ double B[N3];
   __shared__ double Hg[2 * N2];
   for (int i = threadIdx.x; i < 2 * N2; i += blockDim.x) Hg[i] = tab.Hg[i];
   __syncthreads();
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = cells ? cells[blockIdx.x] : blockIdx.x;
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const uint32_t m = mask[cell];
   if (!mask_hanging(m)) return;  // (diag_mapped_direct_kernel)
@@ -1240,7 +1274,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
         }
         WaveSync{}();
       }
-  scatter_zline<K, double, false>(ent, nc, cell, ta, tb, d, diag);
+  scatter_zline<K, double, false>(ent, nc, cell, ta, tb, d, diag, cells != nullptr);
 }
 
 // Constraint distribution: gather G_e and hanging-node interpolation C_e of
@@ -1289,10 +1323,10 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
     rhs_kernel(const int32_t* __restrict__ ent, const uint32_t* __restrict__ mask,
                const int32_t* __restrict__ cell_ijk, int64_t nc, double h0, double lo, OpTab<double, K + 1> tab,
                Gauss1D<K + 1> g, int kind, const double* __restrict__ params, int n_terms, double* __restrict__ b,
-               int nv, const double* __restrict__ geo, int n0) {
+               int nv, const double* __restrict__ geo, int n0, const int32_t* __restrict__ cells) {
   constexpr int N = K + 1, N2 = N * N, N3 = N2 * N;
   __shared__ double B0[N3];
-  const int64_t cell = blockIdx.x;
+  const int64_t cell = cells ? cells[blockIdx.x] : blockIdx.x;  // cells: one colour (deterministic mode)
   const int v = blockIdx.y;
   const int ta = threadIdx.x % N, tb = threadIdx.x / N;
   const uint32_t m = mask[cell];
@@ -1391,7 +1425,7 @@ __global__ void __launch_bounds__((K + 1) * (K + 1))
 #pragma unroll
   for (int r = 0; r < N; ++r) u[r] = B0[tb * N2 + r * N + ta];
   if (hang && hanging_line(m, 1, ta, tb, K)) interp<N, double, true>(tab.H, mask_sub(m, 1), u);
-  scatter_yline<K>(ent, nc, cell, ta, tb, u, b, nv, v);
+  scatter_yline<K>(ent, nc, cell, ta, tb, u, b, nv, v, cells != nullptr);
 }
 
 }  // namespace mfmg
@@ -1497,7 +1531,7 @@ template <int KF, int KC, int NF, typename S, typename T>
 __global__ void __launch_bounds__(TR_THREADS)
     prolongate_kernel(const int32_t* __restrict__ fent, int64_t nfc, const int32_t* __restrict__ cent,
                       const uint32_t* __restrict__ cmask, int64_t ncc, const int32_t* __restrict__ group_coarse,
-                      const int32_t* __restrict__ group_fine, int64_t ngroups, int nchild,
+                      const int32_t* __restrict__ group_fine, int64_t gstride, int nchild,
                       const uint8_t* __restrict__ valence, TrTab<T, NF, KC + 1> tab, const S* __restrict__ src,
                       S* __restrict__ dst, int nv) {
   constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
@@ -1541,7 +1575,7 @@ __global__ void __launch_bounds__(TR_THREADS)
       lattice_local<KF, NF>(J, cy, b);
       lattice_local<KF, NF>(L, cz, c);
       const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
-      const int64_t f = group_fine[child * ngroups + g];
+      const int64_t f = group_fine[child * gstride + g];
       const int s = node_slot(a, b, c, KF);
       // one (cell, slot) pair owns each fine entity: a plain read-modify-write
       if (!(valence[s * nfc + f] & TRANSFER_OWNER)) continue;
@@ -1556,9 +1590,9 @@ template <int KF, int KC, int NF, typename S, typename T>
 __global__ void __launch_bounds__(TR_THREADS)
     restrict_kernel(const int32_t* __restrict__ fent, int64_t nfc, const int32_t* __restrict__ cent,
                     const uint32_t* __restrict__ cmask, int64_t ncc, const int32_t* __restrict__ group_coarse,
-                    const int32_t* __restrict__ group_fine, int64_t ngroups, int nchild,
+                    const int32_t* __restrict__ group_fine, int64_t gstride, int nchild,
                     const uint8_t* __restrict__ valence, TrTab<T, NF, KC + 1> tab, const S* __restrict__ src,
-                    S* __restrict__ dst, int nv) {
+                    S* __restrict__ dst, int nv, bool plain) {
   constexpr int NC = KC + 1, NC3 = NC * NC * NC, NF3 = NF * NF * NF;
   constexpr bool IDENT = (NF == NC) && (KF == KC);
   constexpr int VB = transfer_vb<NF, NC, T>();
@@ -1581,7 +1615,7 @@ __global__ void __launch_bounds__(TR_THREADS)
       lattice_local<KF, NF>(J, cy, b);
       lattice_local<KF, NF>(L, cz, c);
       const int child = nchild == 8 ? cx + 2 * cy + 4 * cz : 0;
-      const int64_t f = group_fine[child * ngroups + g];
+      const int64_t f = group_fine[child * gstride + g];
       const int s = node_slot(a, b, c, KF);
       T y = T(0);
       if (valence[s * nfc + f] & TRANSFER_OWNER) {  // each fine value enters once
@@ -1607,7 +1641,7 @@ __global__ void __launch_bounds__(TR_THREADS)
       const int32_t e = cent[s * ncc + cc];
       if (e < 0) continue;
       add_to<S, T>(&dst[static_cast<int64_t>(e + node_offset(a, b, c, KC)) * nv + v0 + vv], X[i * VB + vv],
-                   s == 26);
+                   plain || s == 26);
     }
   }
 }
@@ -1832,8 +1866,8 @@ void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
   check_launch();
 }
 
-template <int K, typename S, int FK, int GEO>
-void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+template <int K, typename S, int FK, int GEO, bool DET>
+void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
   using T = typename Acc<S>::type;
   constexpr int N = K + 1;
   if (c.n_cells == 0) return;
@@ -1849,7 +1883,7 @@ void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const Fused
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T, FK, GEO>), BATCH_WAVES * 64, 0) !=
+            &per_cu, reinterpret_cast<const void*>(&vmult_batch_kernel<K, S, T, FK, GEO, DET>), BATCH_WAVES * 64, 0) !=
             hipSuccess) {
       (void)hipGetLastError();
       return int64_t(0);
@@ -1859,7 +1893,7 @@ void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const Fused
   const int64_t nb = c.n_batches;
   int64_t blocks = 8 * ((nb + 7) / 8);
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
-  vmult_batch_kernel<K, S, T, FK, GEO><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
+  vmult_batch_kernel<K, S, T, FK, GEO, DET><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0, mt);
   check_launch();
@@ -1868,6 +1902,12 @@ void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const Fused
         c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
     check_launch();
   }
+}
+
+template <int K, typename S, int FK, int GEO>
+void vmult_kg(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+  if (c.deterministic) vmult_kgd<K, S, FK, GEO, true>(c, nv, dst, src, f, s);
+  else vmult_kgd<K, S, FK, GEO, false>(c, nv, dst, src, f, s);
 }
 
 template <int K, typename S, int FK>
@@ -1899,6 +1939,20 @@ void vmult_s(const CellView& c, int nv, void* dst, const void* src, const FusedS
   }
 }
 
+// One launch over all cells (cells = NULL: block i is cell i), or in the
+// deterministic mode one launch per colour over that colour's cell list.
+template <typename F>
+void for_colours(const CellView& c, F launch) {
+  if (!c.deterministic) {
+    launch(static_cast<unsigned>(c.n_cells), static_cast<const int32_t*>(nullptr));
+    return;
+  }
+  for (int k = 0; k < c.n_colors; ++k) {
+    const int64_t n = c.color_off[k + 1] - c.color_off[k];
+    if (n > 0) launch(static_cast<unsigned>(n), c.color_cells + c.color_off[k]);
+  }
+}
+
 template <int K>
 void diag_k(const CellView& c, double* diag, hipStream_t s) {
   constexpr int N = K + 1;
@@ -1920,17 +1974,21 @@ void diag_k(const CellView& c, double* diag, hipStream_t s) {
       return r;
     }();
     const double* geo = static_cast<const double*>(c.geo64);
-    diag_mapped_direct_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(
-        c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, dt, diag);
-    check_launch();
-    diag_mapped_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(
-        c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, tab2, diag);
-    check_launch();
+    for_colours(c, [&](unsigned n, const int32_t* cells) {
+      diag_mapped_direct_kernel<K><<<n, N * N, 0, s>>>(c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, dt, diag,
+                                                       cells);
+      check_launch();
+      diag_mapped_kernel<K><<<n, N * N, 0, s>>>(c.ent, c.mask, c.n_cells, geo, c.ijk, c.geo_n0, mt, tab2, diag,
+                                                cells);
+      check_launch();
+    });
     return;
   }
   static const OpTab<double, N> tab = make_optab<double, N>();
-  diag_kernel<K><<<static_cast<unsigned>(c.n_cells), N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab, diag);
-  check_launch();
+  for_colours(c, [&](unsigned n, const int32_t* cells) {
+    diag_kernel<K><<<n, N * N, 0, s>>>(c.ent, c.mask, c.n_cells, c.h0, tab, diag, cells);
+    check_launch();
+  });
 }
 
 template <int K>
@@ -1940,10 +1998,12 @@ void rhs_k(const CellView& c, int kind, const double* params, int n_terms, int n
   if (c.n_cells == 0) return;
   static const OpTab<double, N> tab = make_optab<double, N>();
   static const Gauss1D<N> g = make_gauss<N>();
-  dim3 grid(static_cast<unsigned>(c.n_cells), nv);
-  rhs_kernel<K><<<grid, N * N, 0, s>>>(c.ent, c.mask, c.ijk, c.n_cells, c.h0, c.lo, tab, g, kind, params,
-                                       n_terms, b, nv, static_cast<const double*>(c.geo64), c.geo_n0);
-  check_launch();
+  for_colours(c, [&](unsigned n, const int32_t* cells) {
+    dim3 grid(n, nv);
+    rhs_kernel<K><<<grid, N * N, 0, s>>>(c.ent, c.mask, c.ijk, c.n_cells, c.h0, c.lo, tab, g, kind, params,
+                                         n_terms, b, nv, static_cast<const double*>(c.geo64), c.geo_n0, cells);
+    check_launch();
+  });
 }
 
 template <typename T, int NF, int NC>
@@ -1975,16 +2035,28 @@ void transfer_launch(bool prolong, const CellView& f, const CellView& c, const T
   using T = typename Acc<S>::type;
   if (ng == 0) return;
   static const TrTab<T, NF, KC + 1> tab = make_trtab<T, NF, KC + 1>(KF, KC);
-  dim3 grid(static_cast<unsigned>(ng));
-  if (prolong)
-    prolongate_kernel<KF, KC, NF, S, T><<<grid, TR_THREADS, 0, s>>>(
+  if (prolong) {  // each fine DoF has one writer: no colouring needed
+    prolongate_kernel<KF, KC, NF, S, T><<<static_cast<unsigned>(ng), TR_THREADS, 0, s>>>(
         f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc, gf, ng, nchild, t.valence, tab,
         static_cast<const S*>(src), static_cast<S*>(dst), nv);
-  else
-    restrict_kernel<KF, KC, NF, S, T><<<grid, TR_THREADS, 0, s>>>(
-        f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc, gf, ng, nchild, t.valence, tab,
-        static_cast<const S*>(src), static_cast<S*>(dst), nv);
-  check_launch();
+    check_launch();
+    return;
+  }
+  // restriction: one launch, or in the deterministic mode one per colour of
+  // the group list (plain adds into the coarse DoFs)
+  const int64_t* off = nchild == 1 ? t.ident_off : t.refined_off;
+  const int n_col = nchild == 1 ? t.n_ident_colors : t.n_refined_colors;
+  const int64_t whole[2] = {0, ng};
+  const bool det = t.deterministic && off != nullptr;
+  const int64_t* o = det ? off : whole;
+  for (int k = 0; k < (det ? n_col : 1); ++k) {
+    const int64_t n = o[k + 1] - o[k];
+    if (n == 0) continue;
+    restrict_kernel<KF, KC, NF, S, T><<<static_cast<unsigned>(n), TR_THREADS, 0, s>>>(
+        f.ent, f.n_cells, c.ent, c.mask, c.n_cells, gc + o[k], gf + o[k], ng, nchild, t.valence, tab,
+        static_cast<const S*>(src), static_cast<S*>(dst), nv, det);
+    check_launch();
+  }
 }
 
 template <int K, typename S>

@@ -42,6 +42,15 @@ struct CellView {
   const void* geo64 = nullptr;
   const void* geo32 = nullptr;
   int geo_n0 = 0;
+  // deterministic mode: the operator adds its cells' contributions in cell
+  // order; the diagonal and the load vector run colour by colour (no two
+  // cells of a colour share an entity, plain adds).  color_cells (device)
+  // lists the cells colour by colour, color_off (host, n_colors + 1) the
+  // colour ranges.
+  bool deterministic = false;
+  const int32_t* color_cells = nullptr;
+  const int64_t* color_off = nullptr;
+  int n_colors = 0;
 };
 
 // An elementwise step fused into the operator's output: for every DoF i and
@@ -69,6 +78,15 @@ struct TransferView {
   const int32_t* refined_fine = nullptr;  // [8][n_refined]
   int64_t n_refined = 0;
   const uint8_t* valence = nullptr;       // [27][n_fine_cells]
+  // deterministic mode: the restriction runs the groups colour by colour (no
+  // two groups of a colour share a coarse entity, plain adds); the group
+  // lists are in colour order and ident_off / refined_off (host, colours + 1)
+  // give the ranges
+  bool deterministic = false;
+  const int64_t* ident_off = nullptr;
+  int n_ident_colors = 0;
+  const int64_t* refined_off = nullptr;
+  int n_refined_colors = 0;
 };
 
 // dtype: MFMG_F64 / MFMG_F32 / MFMG_BF16 for the vectors named "S"; the

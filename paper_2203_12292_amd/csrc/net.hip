@@ -254,59 +254,103 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// Step 2 (one block): the exact coarse operator checks the prediction y; if
+// Step 2: the exact coarse operator checks the prediction y; if
 // ||b0 - A0 y|| > tau ||b0|| the exact solution A0^{-1} b0 is used instead.
-// mode 2: no coarse correction (x = 0).
+// Three kernels, all on the stream (no host synchronisation):
+//  net_resid: one wavefront per row i, r_i = b_i - (A0 y)_i read along the
+//    row (adjacent lanes, adjacent entries); per block the sums of r_i^2 and
+//    b_i^2 into partial[2 block + {0, 1}];
+//  net_decide (one block): the two norms from the partials in block order,
+//    the decision (flag: 0 accept, 1 reject, 2 zero right-hand side) and the
+//    counters;
+//  net_apply: one wavefront per row, x_i = y_i (accept), 0, or
+//    (A0^{-1} b0)_i (reject; the inverse is read only then).
+constexpr int NET_ROWS = 4;  // rows (wavefronts) per block of the dense kernels
+
+inline unsigned net_row_blocks(int n0) { return static_cast<unsigned>((n0 + NET_ROWS - 1) / NET_ROWS); }
+
 template <typename S>
-__global__ void __launch_bounds__(256)
-    net_check(int n0, const double* __restrict__ A, const double* __restrict__ Ainv, double tau, int mode,
-              const S* __restrict__ b, S* __restrict__ x, const double* __restrict__ work,
-              int* __restrict__ counters, double* __restrict__ relsum) {
-  __shared__ double red[256];
-  const double* y = work + n0;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-    const double v = load_as<double>(b[i]);
-    s += v * v;
+__global__ void __launch_bounds__(64 * NET_ROWS)
+    net_resid(int n0, const double* __restrict__ A, const S* __restrict__ b, const double* __restrict__ y,
+              double* __restrict__ partial) {
+  __shared__ double red[2 * NET_ROWS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+  const int row = blockIdx.x * NET_ROWS + w;
+  double rr = 0.0, bb = 0.0;
+  if (row < n0) {
+    double s = 0.0;
+    for (int j = lane; j < n0; j += 64) s += A[static_cast<int64_t>(row) * n0 + j] * y[j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    const double bi = load_as<double>(b[row]);
+    const double r = bi - s;
+    rr = r * r;
+    bb = bi * bi;
   }
-  red[threadIdx.x] = s;
+  if (lane == 0) {
+    red[2 * w] = rr;
+    red[2 * w + 1] = bb;
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double nb = sqrt(red[0]);
-  __syncthreads();
-  if (nb == 0.0 || mode == 2) {
-    for (int i = threadIdx.x; i < n0; i += blockDim.x) x[i] = store_as<S>(0.0);
-    return;
-  }
-  double rs = 0.0;
-  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-    double r = load_as<double>(b[i]);
-    for (int j = 0; j < n0; ++j) r -= A[static_cast<int64_t>(i) * n0 + j] * y[j];
-    rs += r * r;
-  }
-  red[threadIdx.x] = rs;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double rel = sqrt(red[0]) / nb;
-  const bool accept = rel <= tau;
   if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int q = 0; q < NET_ROWS; ++q) {
+      a += red[2 * q];
+      c += red[2 * q + 1];
+    }
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = c;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    net_decide(int n_blocks, double tau, const double* __restrict__ partial, double* __restrict__ flag,
+               int* __restrict__ counters, double* __restrict__ relsum) {
+  __shared__ double ra[256], rb[256];
+  double a = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n_blocks; i += 256) {
+    a += partial[2 * i];
+    c += partial[2 * i + 1];
+  }
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      ra[threadIdx.x] += ra[threadIdx.x + w];
+      rb[threadIdx.x] += rb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nb = sqrt(rb[0]);
+    if (nb == 0.0) {
+      flag[0] = 2.0;
+      return;
+    }
+    const double rel = sqrt(ra[0]) / nb;
+    const bool accept = rel <= tau;
+    flag[0] = accept ? 0.0 : 1.0;
     atomicAdd(&counters[accept ? 0 : 1], 1);
     atomicAdd(relsum, rel);
   }
-  if (accept) {
-    for (int i = threadIdx.x; i < n0; i += blockDim.x) x[i] = store_as<S>(y[i]);
-  } else {
-    for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-      double v = 0.0;
-      for (int j = 0; j < n0; ++j) v += Ainv[static_cast<int64_t>(i) * n0 + j] * load_as<double>(b[j]);
-      x[i] = store_as<S>(v);
-    }
+}
+
+// mode 2 (no coarse correction) writes zeros without reading the flag
+template <typename S>
+__global__ void __launch_bounds__(64 * NET_ROWS)
+    net_apply(int n0, int mode, const double* __restrict__ Ainv, const S* __restrict__ b,
+              const double* __restrict__ y, const double* __restrict__ flag, S* __restrict__ x) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * NET_ROWS + threadIdx.x / 64;
+  if (row >= n0) return;
+  const double f = mode == 2 ? 2.0 : flag[0];
+  if (f == 1.0) {
+    double v = 0.0;
+    for (int j = lane; j < n0; j += 64) v += Ainv[static_cast<int64_t>(row) * n0 + j] * load_as<double>(b[j]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) x[row] = store_as<S>(v);
+  } else if (lane == 0) {
+    x[row] = store_as<S>(f == 0.0 ? y[row] : 0.0);
   }
 }
 
@@ -356,7 +400,9 @@ void net_setup(Context& ctx, const LevelDofs& L0) {
   N.params.alloc(N.n_params);
   std::vector<float> zeros(N.n_params, 0.0f);
   MFMG_HIP(hipMemcpy(N.params.ptr, zeros.data(), N.n_params * 4, hipMemcpyHostToDevice));
-  N.work.alloc(2 * static_cast<size_t>(N.n0) + 2);
+  // y (n0), a spare n0, the decision flag (8 slots) and 2 partial sums per
+  // block of the dense check
+  N.work.alloc(2 * static_cast<size_t>(N.n0) + 8 + 2 * static_cast<size_t>(net_row_blocks(N.n0)));
   N.counters.alloc(2);
   MFMG_HIP(hipMemset(N.counters.ptr, 0, 8));
   N.relsum.alloc(1);
@@ -490,8 +536,14 @@ static void net_coarse_solve_t(Context& ctx, S* x, const S* b, hipStream_t s) {
     net_infer_cells<S><<<N.n_cells, 64, 0, s>>>(N.n0, N.nq, N.params.ptr, N.node_dof.ptr, N.inv_val.ptr,
                                                  N.centre.ptr, b, N.work.ptr);
   }
-  net_check<S><<<1, 256, 0, s>>>(N.n0, ctx.coarse_A64.ptr, ctx.coarse_inv64.ptr, N.tau, mode, b, x, N.work.ptr,
-                                 N.counters.ptr, N.relsum.ptr);
+  const unsigned nbk = net_row_blocks(N.n0);
+  double* flag = N.work.ptr + 2 * static_cast<int64_t>(N.n0);
+  double* partial = flag + 8;
+  if (mode == 1) {
+    net_resid<S><<<nbk, 64 * NET_ROWS, 0, s>>>(N.n0, ctx.coarse_A64.ptr, b, N.work.ptr + N.n0, partial);
+    net_decide<<<1, 256, 0, s>>>(static_cast<int>(nbk), N.tau, partial, flag, N.counters.ptr, N.relsum.ptr);
+  }
+  net_apply<S><<<nbk, 64 * NET_ROWS, 0, s>>>(N.n0, mode, ctx.coarse_inv64.ptr, b, N.work.ptr + N.n0, flag, x);
   check_launch();
 }
 

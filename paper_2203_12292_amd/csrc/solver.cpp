@@ -266,6 +266,15 @@ void init_level(Context& ctx, Level& L, const LevelDofs& H, double lo, bool work
     L.tmp_cast.alloc(nrhs * 8);
   }
   L.t.alloc(nrhs * 8);
+  if (ctx.desc.deterministic) {
+    std::vector<int32_t> cells;
+    colour_cells(H, cells, L.color_off);
+    L.color_cells.upload(cells);
+    L.view.deterministic = true;
+    L.view.color_cells = L.color_cells.ptr;
+    L.view.color_off = L.color_off.data();
+    L.view.n_colors = static_cast<int>(L.color_off.size()) - 1;
+  }
   L.diag.alloc(L.n_dofs);
   L.dinv.alloc(L.n_dofs * 8 * 2);  // double copy, then float copy
   launch_diagonal(L.view, L.diag.ptr, s);
@@ -275,6 +284,15 @@ void init_level(Context& ctx, Level& L, const LevelDofs& H, double lo, bool work
 
 void init_transfer(Level& L, const TransferDofs& T, bool poly) {
   L.has_transfer = true;
+  if (!T.ident_off.empty() || !T.refined_off.empty()) {  // coloured groups (deterministic mode)
+    L.tr_ident_off = T.ident_off;
+    L.tr_refined_off = T.refined_off;
+    L.tview.deterministic = true;
+    L.tview.ident_off = L.tr_ident_off.data();
+    L.tview.n_ident_colors = static_cast<int>(L.tr_ident_off.size()) - 1;
+    L.tview.refined_off = L.tr_refined_off.data();
+    L.tview.n_refined_colors = static_cast<int>(L.tr_refined_off.size()) - 1;
+  }
   L.tr_ident_c.upload(T.ident_coarse);
   L.tr_ident_f.upload(T.ident_fine);
   L.tr_ref_c.upload(T.refined_coarse);
@@ -346,7 +364,8 @@ void setup_local_smoothing(Context& ctx, const mfmg_level_desc& desc, std::vecto
   }
   for (int l = 1; l < nl; ++l) {
     const bool poly = ctx.levels[l - 1].k != ctx.levels[l].k;
-    init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly, !poly), poly);
+    init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly, !poly, ctx.desc.deterministic != 0),
+                  poly);
   }
   // the active mesh (the outer solver's operator), FP64
   LevelDofs A = build_level_dofs(tree, desc.degree, true, false, -1, &ctx.coef);
@@ -453,7 +472,8 @@ void setup_context(Context& ctx, const mfmg_mesh_s& mesh, const mfmg_level_desc&
     }
     for (int l = 1; l < nl; ++l) {
       const bool poly = ctx.levels[l - 1].mesh == ctx.levels[l].mesh;
-      init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly), poly);
+      init_transfer(ctx.levels[l], build_transfer(host[l], host[l - 1], poly, false, ctx.desc.deterministic != 0),
+                    poly);
     }
   }
   const int nl = static_cast<int>(ctx.levels.size());

@@ -45,7 +45,8 @@ class LevelDesc(C.Structure):
                 ("cheb_degree", C.c_int), ("smoothing_range", C.c_double), ("eig_safety", C.c_double),
                 ("eig_iterations", C.c_int), ("max_rhs", C.c_int), ("drop_coarse", C.c_int),
                 ("coef_kind", C.c_int), ("coef_params", C.c_double * 8), ("graph_vcycle", C.c_int),
-                ("fmg_start", C.c_int), ("geom_kind", C.c_int), ("geom_params", C.c_double * 8)]
+                ("fmg_start", C.c_int), ("geom_kind", C.c_int), ("geom_params", C.c_double * 8),
+                ("deterministic", C.c_int)]
 
 
 class NetTrainDesc(C.Structure):
@@ -256,7 +257,7 @@ class Solver:
 
     def __init__(self, mesh, degree, scheme=SCHEME_H, level_dtypes=None, dirichlet=True, cheb_degree=3,
                  max_rhs=1, smoothing_range=20.0, eig_safety=1.2, eig_iterations=15, drop_coarse=0,
-                 coef=None, graph_vcycle=False, fmg_start=False, geometry=None):
+                 coef=None, graph_vcycle=False, fmg_start=False, geometry=None, deterministic=False):
         d = LevelDesc()
         d.degree, d.scheme, d.dirichlet = degree, scheme, int(dirichlet)
         level_dtypes = list(level_dtypes or [])
@@ -266,6 +267,7 @@ class Solver:
         d.cheb_degree, d.smoothing_range, d.eig_safety = cheb_degree, smoothing_range, eig_safety
         d.eig_iterations, d.max_rhs, d.drop_coarse = eig_iterations, max_rhs, drop_coarse
         d.graph_vcycle, d.fmg_start = int(graph_vcycle), int(fmg_start)
+        d.deterministic = int(deterministic)
         if coef is not None:  # a synth coefficient descriptor {"kind": k, "params": [...]}
             d.coef_kind = coef["kind"]
             for i, v in enumerate(coef["params"]):

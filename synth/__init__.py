@@ -124,6 +124,13 @@ def shell_mesh(L):
                       (BAND, (0.0, 0.0, 0.0, 0.335, 0.39))])
 
 
+# the paper's two test shapes at about 17M Q4 DoFs, and a uniform mesh of
+# that size built the same way from one cell (hanging-node overhead)
+OCTANT7 = octant_mesh(7)
+SHELL8 = shell_mesh(8)
+UNIFORM64 = mesh_desc("uniform64", 1, -1.0, 1.0, 6, [])
+
+
 def small_mesh(name="tiny2", n0=2, n_global=0, n_steps=2, r=0.6, lo=0.0, hi=1.0):
     """Very small hanging-node meshes for brute-force checks."""
     return ball_mesh(name, n0, n_global, n_steps, r=r, lo=lo, hi=hi)
