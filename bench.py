@@ -465,43 +465,71 @@ def ls_sweep():
                 del S
 
 
-def kernel_summary(trace_dir, pmc_dirs, title, commands, top=10):
+def kernel_summary(trace_dir, pmc_dirs, title, commands, top=10, last=0):
     """Markdown summary of a rocprofv3 run of one --profile workload: the
     kernels by total time (dispatch count, median and mean duration) from
     the kernel trace, and the mean of each counter per kernel from the --pmc
-    runs (the largest grid of each kernel name, i.e. the finest level)."""
+    runs.  With last > 0 only the last `last` dispatches of each kernel name
+    count (the timed loop of the workload, after its set-up); otherwise the
+    largest grid of each name."""
     import numpy as np
     rows = []
     for path in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
         with open(path, newline="") as fh:
             for r in csv.DictReader(fh):
                 grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-                rows.append((_kname(r["Kernel_Name"]), grid,
+                rows.append((int(r["Start_Timestamp"]), _kname(r["Kernel_Name"]), grid,
                              (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    rows.sort()
+    if last > 0:
+        keep = {}
+        for row in rows:
+            keep.setdefault(row[1], []).append(row)
+        rows = sorted(r for v in keep.values() for r in v[-last:])
     by = {}
-    for name, grid, us in rows:
+    for _, name, grid, us in rows:
         by.setdefault((name, grid), []).append(us)
     lines = [f"# {title}", "", "Commands:", ""] + [f"    {c}" for c in commands] + [""]
     lines += ["| kernel | grid (threads) | dispatches | median us | mean us | total ms |", "|---|---|---|---|---|---|"]
+    top_names = []
     for (name, grid), v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:top]:
         lines.append(f"| `{name}` | {grid} | {len(v)} | {np.median(v):.1f} | {np.mean(v):.1f} | {sum(v) / 1e3:.2f} |")
+        top_names.append(name)
     for d in pmc_dirs:
-        vals = {}
+        recs = []
         for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             with open(path, newline="") as fh:
                 for r in csv.DictReader(fh):
-                    key = (_kname(r["Kernel_Name"]), int(r["Grid_Size"]))
-                    vals.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                    recs.append((int(r["Dispatch_Id"]), _kname(r["Kernel_Name"]), int(r["Grid_Size"]),
+                                 r["Counter_Name"], float(r["Counter_Value"])))
+        recs.sort()
         best = {}
-        for (name, grid), cs in vals.items():
-            if name not in best or grid > best[name][0]:
-                best[name] = (grid, cs)
+        if last > 0:
+            ids = {}
+            for did, name, grid, _, _ in recs:
+                lst = ids.setdefault(name, [])
+                if not lst or lst[-1] != did:
+                    lst.append(did)
+            chosen = {name: set(v[-last:]) for name, v in ids.items()}
+            for did, name, grid, cn, cv in recs:
+                if did in chosen[name]:
+                    best.setdefault(name, (grid, {}))[1].setdefault(cn, []).append(cv)
+        else:
+            vals = {}
+            for _, name, grid, cn, cv in recs:
+                vals.setdefault((name, grid), {}).setdefault(cn, []).append(cv)
+            for (name, grid), cs in vals.items():
+                if name not in best or grid > best[name][0]:
+                    best[name] = (grid, cs)
         if not best:
             continue
         counters = sorted({c for _, cs in best.values() for c in cs})
-        lines += ["", f"Counters ({os.path.basename(d.rstrip('/'))}; mean per dispatch, largest grid of each kernel):", ""]
+        which = f"last {last} dispatches of each kernel" if last > 0 else "largest grid of each kernel"
+        lines += ["", f"Counters ({os.path.basename(d.rstrip('/'))}; mean per dispatch, {which}):", ""]
         lines += ["| kernel | grid | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
-        for name, (grid, cs) in sorted(best.items(), key=lambda kv: -kv[1][0])[:top]:
+        order = [n for n in dict.fromkeys(top_names) if n in best] or sorted(best, key=lambda n: -best[n][0])[:top]
+        for name in order:
+            grid, cs = best[name]
             lines.append(f"| `{name}` | {grid} | " +
                          " | ".join(f"{np.mean(cs[c]):.4g}" if c in cs else "" for c in counters) + " |")
     return "\n".join(lines)
@@ -525,6 +553,8 @@ def main():
     ap.add_argument("--kernel-summary", nargs="+", metavar="DIR",
                     help="print a markdown summary of a kernel-trace folder and --pmc folders and exit (no GPU)")
     ap.add_argument("--summary-title", default="rocprofv3 summary")
+    ap.add_argument("--summary-last", type=int, default=0,
+                    help="count only the last N dispatches of each kernel (the timed loop)")
     ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
                     help="run only the kernels of one workload --steps times (for rocprofv3) and exit")
     args = ap.parse_args()
@@ -532,7 +562,8 @@ def main():
         ls_sweep()
         return
     if args.kernel_summary:
-        print(kernel_summary(args.kernel_summary[0], args.kernel_summary[1:], args.summary_title, args.pmc_command))
+        print(kernel_summary(args.kernel_summary[0], args.kernel_summary[1:], args.summary_title, args.pmc_command,
+                             last=args.summary_last))
         return
     if args.profile:
         run_profile_workload(args.profile, args.steps, args.warmup)

@@ -230,16 +230,26 @@ __device__ __forceinline__ void interp_const(T (&u)[N]) {
   for (int i = 0; i < N; ++i) u[i] = out[i];
 }
 
-// u <- H_s u (H_s^T u if TRANS) for the hanging lines of a cell; UNI: s is
-// wavefront-uniform and the matrices come from constant memory, otherwise
-// from their LDS copy Hg
+// u <- H_s u (H_s^T u if TRANS) for the hanging lines of a cell, from the
+// constant-memory table.  UNI: s is wavefront-uniform, a uniform branch picks
+// the half.  Otherwise s differs between the cells of a wavefront: the halves
+// are mirror images, H_1 = J H_0 J with J the reversal of the node order (the
+// nodes are symmetric about the midpoint and l_j(1 - t) = l_{n-1-j}(t)), so
+// each lane reverses its line where s = 1, applies H_0 (scalar operands) and
+// reverses back: 2n selects instead of n^2 LDS reads of the table.
 template <int N, typename T, bool TRANS, bool UNI>
 __device__ __forceinline__ void hang_interp(const T* __restrict__ Hg, int s, T (&u)[N]) {
+  (void)Hg;
   if constexpr (UNI) {
     if (s) interp_const<N, T, TRANS, 1>(u);
     else interp_const<N, T, TRANS, 0>(u);
   } else {
-    interp_lds<N, T, TRANS>(Hg, s, u);
+    T w[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) w[j] = s ? u[N - 1 - j] : u[j];
+    interp_const<N, T, TRANS, 0>(w);
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = s ? w[N - 1 - i] : w[i];
   }
 }
 
@@ -1873,7 +1883,7 @@ void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const Fuse
   if (c.n_cells == 0) return;
   static const OpTab2<T, N> tab = make_optab2<T, N>();
   static const MapTab<T, N> mt = make_maptab<T, N>();
-  if constexpr (cells_per_wave(N) == 1 && GEO == 0) ensure_hg_table<T, N>();
+  if constexpr (GEO == 0) ensure_hg_table<T, N>();
   const T* geo = nullptr;
   if constexpr (GEO != 0) geo = static_cast<const T*>(sizeof(T) == 8 ? c.geo64 : c.geo32);
   // persistent blocks: as many as are resident on the device at once (a
