@@ -81,7 +81,14 @@ def _pmc_rows(folder, counter):
 
 def _kname(name):
     """Kernel name without return type, namespace and argument list."""
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "").replace("mfmg::", "").strip()
+
+
+# the plain FP64 Q4 operator on axis-aligned cells (no fused step, default
+# mode) and its shared-DoF reduction
+_Q4_VMULT = re.compile(r"vmult_batch_kernel<4, double, double, 0(, 0)?(, false)?>$")
+_Q4_REDUCE = "reduce_shared_kernel<double, double, 0>"
 
 
 def trace_summary(trace_csv, bench_json, commands):
@@ -103,9 +110,9 @@ def trace_summary(trace_csv, bench_json, commands):
     # finest-level applications: each batch-kernel dispatch followed by its
     # shared-DoF reduction; the finest level is the pair whose reduction has
     # the largest grid (the reduction is sized by the level's shared DoFs)
-    name_vm, name_red = "vmult_batch_kernel<4, double, double, 0>", "reduce_shared_kernel<double, double, 0>"
     pairs = [(rows[q][2], rows[q + 1][2], rows[q][3], rows[q + 1][3]) for q in range(len(rows) - 1)
-             if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
+             if _Q4_VMULT.match(rows[q][1]) and rows[q + 1][1] == _Q4_REDUCE]
+    vm_name = next(rows[q][1] for q in range(len(rows)) if _Q4_VMULT.match(rows[q][1]))
     red_g = max(p[1] for p in pairs)
     sel = [p for p in pairs if p[1] == red_g]
     vm = (sel[0][0], len(sel), float(np.mean([p[2] for p in sel])))
@@ -130,8 +137,8 @@ def trace_summary(trace_csv, bench_json, commands):
         "",
         "| finest-level kernel | grid (work items) | dispatches | average |",
         "|---|---:|---:|---:|",
-        f"| vmult_batch_kernel<4, double, double, 0> | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
-        f"| reduce_shared_kernel<double, double, 0> | {red[0]} | {red[1]} | {red[2]:.1f} us |",
+        f"| {vm_name} | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
+        f"| {_Q4_REDUCE} | {red[0]} | {red[1]} | {red[2]:.1f} us |",
         f"| sum = one operator application | | | {vm[2] + red[2]:.1f} us |",
         "",
         f"The benchmark's HIP-event average over its {bench['steps']} timed steps in the same run: {ev:.1f} us",
@@ -160,9 +167,8 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         """(mean value, dispatches, grid) of the finest-level batch kernel, of
         its reduction (pairs whose reduction has the largest grid) and of the
         calibration copy (elementwise kernel with the largest grid)."""
-        name_vm, name_red = "vmult_batch_kernel<4, double, double, 0>", "reduce_shared_kernel<double, double, 0>"
         pairs = [(rows[q], rows[q + 1]) for q in range(len(rows) - 1)
-                 if rows[q][1] == name_vm and rows[q + 1][1] == name_red]
+                 if _Q4_VMULT.match(rows[q][1]) and rows[q + 1][1] == _Q4_REDUCE]
         red_g = max(b[2] for _, b in pairs)
         sel = [(a, b) for a, b in pairs if b[2] == red_g]
         cp = [r for r in rows if "elementwise_kernel" in r[1]]
@@ -192,7 +198,7 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         "| kernel | grid | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |",
         "|---|---:|---:|---:|---:|",
     ]
-    for key, name in (("vmult", "vmult_batch_kernel<4, double, double, 0>"), ("reduce", "reduce_shared_kernel<double, double, 0>"),
+    for key, name in (("vmult", "vmult_batch_kernel<4, double, double, 0, ...> (plain FP64 operator)"), ("reduce", _Q4_REDUCE),
                       ("copy", "elementwise kernel y = 1.0 * x (calibration, n doubles)")):
         fv, fd, fg = res["fetch"][key]
         wv, _, _ = res["write"][key]
