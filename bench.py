@@ -349,6 +349,7 @@ PROFILE_WORKLOADS = {
     "q4_f64_vmult": ("CFG2", 4, "h_then_p", "f64", 1, "vmult"),
     "q4_f32_vmult": ("CFG2", 4, "h_then_p", "f32", 1, "vmult"),
     "q6_f32x8_vmult": ("CFG4", 6, "p_then_h", "f32", 8, "vmult"),
+    "q6_f32x1_vmult": ("CFG4", 6, "p_then_h", "f32", 1, "vmult"),
     "q6_f32x8_transfer": ("CFG4", 6, "p_then_h", "f32", 8, "transfer"),
     "q6_f32x8_smooth": ("CFG4", 6, "p_then_h", "f32", 8, "smooth"),
     "q4_f64_smooth": ("CFG2", 4, "h_then_p", "f64", 1, "smooth"),
