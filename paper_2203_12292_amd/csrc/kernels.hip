@@ -927,24 +927,22 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
   const int64_t per = (nb + 7) / 8;
   const int64_t lo = (blockIdx.x % 8) * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
-  const int64_t stride = gridDim.x / 8;
   // several interleaved vectors: nv blocks of one XCD (consecutive block
   // indices there) take the same batch at the same time, one vector each,
   // so that the nv values of a DoF, adjacent in memory, are read once into
   // that XCD's L2 and their partial-line writes meet there.  (Vectors one
   // after the other in one block left a whole pass of the other blocks'
   // traffic between two passes over a line, so that it was fetched and
-  // written back up to nv times.)  With fewer blocks per XCD than vectors,
-  // one block runs the vectors one after the other.
-  const bool together = nv > 1 && stride >= nv;
-  const int64_t j = blockIdx.x / 8;
-  const int64_t groups = together ? stride / nv : stride;
-  if (j >= (together ? groups * nv : stride)) return;  // (whole block: no barrier passed yet)
-  const int64_t g = together ? j / nv : j;
+  // written back up to nv times.)  The launch gives every XCD at least nv
+  // blocks.
+  const int groups = static_cast<int>(gridDim.x / 8) / nv;
+  const int j = static_cast<int>(blockIdx.x / 8);
+  if (j >= groups * nv) return;  // (whole block: no barrier passed yet)
+  const int v = j % nv;
+  const int64_t b0 = lo + j / nv;
   for (int64_t w = 0;; ++w) {
-    const int64_t b = lo + g + (together ? w : w / nv) * groups;
+    const int64_t b = b0 + w * groups;
     if (b >= hi) break;
-    const int v = together ? static_cast<int>(j % nv) : static_cast<int>(w % nv);
     const int c0 = bcell[b], c1 = bcell[b + 1];
     const int sh0 = bsh[b], nsh = bsh[b + 1] - sh0;
     const int64_t ex0 = n_shared + bex[b];
@@ -1912,6 +1910,7 @@ void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const Fuse
   const int64_t nb = c.n_batches;
   int64_t blocks = 8 * ((nb * nv + 7) / 8);  // (several vectors: one block per (batch, vector) at most)
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
+  if (blocks < 8 * nv) blocks = 8 * nv;  // every XCD runs all vectors of a batch together
   vmult_batch_kernel<K, S, T, FK, GEO, DET><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
       c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0, mt);

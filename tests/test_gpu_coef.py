@@ -175,3 +175,12 @@ def test_set_coefficient(name, k, scheme):
     with pytest.raises(mfmg.MfmgError):
         S.set_coefficient(bad)
     check_against(H, S, P, "after a rejected update")
+
+
+def test_set_coefficient_rejects_local_smoothing():
+    from paper_2203_12292_amd import mfmg
+    S = mfmg.Solver(mfmg.Mesh(DESCS["tiny"]), 2, mfmg.SCHEME_LS)
+    n = S.level_info(S.n_levels - 1)["n_cells"]
+    with pytest.raises(mfmg.MfmgError) as e:
+        S.set_coefficient(torch.ones(n, dtype=torch.float64, device=DEV))
+    assert e.value.code == mfmg.ERR_UNSUPPORTED

@@ -130,3 +130,23 @@ def test_bitwise_repeatable_and_oracle(name, k, scheme, geom):
     err = np.linalg.norm(get(sol[0], P[-1]) - xo) / np.linalg.norm(xo)
     print(f"[deterministic] {name} k={k} {scheme} {geom}: {its[0]} iterations, error {err:.2e}", flush=True)
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("name,k", [("small", 4), ("cfg1", 2)])
+def test_local_smoothing_bitwise_repeatable(name, k):
+    """Local smoothing in the deterministic mode: the solve (copies to and
+    from the levels, edge-truncated smoothers, transfers, load vector) gives
+    the same bits twice in one context and in a second one."""
+    from paper_2203_12292_amd import mfmg
+    mk = lambda: mfmg.Solver(mfmg.Mesh(DESCS[name]), k, mfmg.SCHEME_LS, deterministic=True)
+    A, B = mk(), mk()
+    sols = []
+    for S in (A, A, B):
+        b = torch.zeros(S.n_dofs(), dtype=torch.float64, device=DEV)
+        S.rhs(b)
+        x = torch.zeros_like(b)
+        st = S.solve(x, b, rtol=1e-10, max_it=100)
+        assert st["converged"]
+        sols.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(sols[0], sols[1]) and torch.equal(sols[0], sols[2])
