@@ -85,10 +85,22 @@ def _kname(name):
     return name.split("(")[0].replace("void ", "").replace("mfmg::", "").strip()
 
 
-# the plain FP64 Q4 operator on axis-aligned cells (no fused step, default
-# mode) and its shared-DoF reduction
-_Q4_VMULT = re.compile(r"vmult_batch_kernel<4, double, double, 0(, 0)?(, false)?>$")
-_Q4_REDUCE = "reduce_shared_kernel<double, double, 0>"
+# the plain FP64 Q4 operator on one vector, axis-aligned cells, default mode
+# (fused kind 3: no fused step, the shared DoFs' contributions added to the
+# output atomically) and the clearing of the output's shared DoFs before it
+_Q4_VMULT = re.compile(r"vmult_batch_kernel<4, double, double, 3(, 0)?(, false)?>$")
+_Q4_CLEAR = "clear_shared_kernel<double>"
+
+
+def _q4_pairs(rows):
+    """Finest-level applications in a list of (t0, name, grid, value) rows:
+    each batch-kernel dispatch with the shared-DoF clearing just before it;
+    the finest level is the pair whose clearing has the largest grid (it is
+    sized by the level's shared DoFs).  Returns [(clear row, batch row)]."""
+    pairs = [(rows[q], rows[q + 1]) for q in range(len(rows) - 1)
+             if rows[q][1] == _Q4_CLEAR and _Q4_VMULT.match(rows[q + 1][1])]
+    g = max(a[2] for a, _ in pairs)
+    return [(a, b) for a, b in pairs if a[2] == g]
 
 
 def trace_summary(trace_csv, bench_json, commands):
@@ -107,16 +119,10 @@ def trace_summary(trace_csv, bench_json, commands):
     rows.sort()
     with open(bench_json) as fh:
         bench = json.loads(fh.read().strip().splitlines()[-1])
-    # finest-level applications: each batch-kernel dispatch followed by its
-    # shared-DoF reduction; the finest level is the pair whose reduction has
-    # the largest grid (the reduction is sized by the level's shared DoFs)
-    pairs = [(rows[q][2], rows[q + 1][2], rows[q][3], rows[q + 1][3]) for q in range(len(rows) - 1)
-             if _Q4_VMULT.match(rows[q][1]) and rows[q + 1][1] == _Q4_REDUCE]
-    vm_name = next(rows[q][1] for q in range(len(rows)) if _Q4_VMULT.match(rows[q][1]))
-    red_g = max(p[1] for p in pairs)
-    sel = [p for p in pairs if p[1] == red_g]
-    vm = (sel[0][0], len(sel), float(np.mean([p[2] for p in sel])))
-    red = (red_g, len(sel), float(np.mean([p[3] for p in sel])))
+    sel = _q4_pairs(rows)
+    vm_name = sel[0][1][1]
+    clr = (sel[0][0][2], len(sel), float(np.mean([a[3] for a, _ in sel])))
+    vm = (sel[0][1][2], len(sel), float(np.mean([b[3] for _, b in sel])))
     rows = [(name, g, us) for _, name, g, us in rows]
     ev = bench["roofline"]["avg_launch_ms"] * 1e3
     tot = {}
@@ -137,15 +143,15 @@ def trace_summary(trace_csv, bench_json, commands):
         "",
         "| finest-level kernel | grid (work items) | dispatches | average |",
         "|---|---:|---:|---:|",
+        f"| {_Q4_CLEAR} | {clr[0]} | {clr[1]} | {clr[2]:.1f} us |",
         f"| {vm_name} | {vm[0]} | {vm[1]} | {vm[2]:.1f} us |",
-        f"| {_Q4_REDUCE} | {red[0]} | {red[1]} | {red[2]:.1f} us |",
-        f"| sum = one operator application | | | {vm[2] + red[2]:.1f} us |",
+        f"| sum = one operator application | | | {vm[2] + clr[2]:.1f} us |",
         "",
         f"The benchmark's HIP-event average over its {bench['steps']} timed steps in the same run: {ev:.1f} us",
-        f"per application ({100.0 * abs(ev - vm[2] - red[2]) / ev:.1f} % from the trace).",
+        f"per application ({100.0 * abs(ev - vm[2] - clr[2]) / ev:.1f} % from the trace).",
         "",
         f"Algorithmic traffic 16 B/DoF = {alg / 1e9:.3f} GB per application -> "
-        f"{alg / ((vm[2] + red[2]) * 1e-6) / 1e9:.0f} GB/s from the trace,",
+        f"{alg / ((vm[2] + clr[2]) * 1e-6) / 1e9:.0f} GB/s from the trace,",
         f"{bench['roofline']['achieved']:.0f} GB/s from the events "
         f"({100.0 * bench['roofline']['frac']:.1f} % of 8 TB/s).",
         "",
@@ -159,23 +165,20 @@ def trace_summary(trace_csv, bench_json, commands):
 
 def pmc_summary(fetch_dir, write_dir, n, commands):
     """Markdown summary of the two counter passes: HBM bytes of one finest-level
-    operator application (batch kernel + shared-DoF reduction), calibrated by a
+    operator application (shared-DoF clearing + batch kernel), calibrated by a
     plain elementwise kernel that reads and writes n doubles."""
     import numpy as np
 
     def pick(rows):
-        """(mean value, dispatches, grid) of the finest-level batch kernel, of
-        its reduction (pairs whose reduction has the largest grid) and of the
-        calibration copy (elementwise kernel with the largest grid)."""
-        pairs = [(rows[q], rows[q + 1]) for q in range(len(rows) - 1)
-                 if _Q4_VMULT.match(rows[q][1]) and rows[q + 1][1] == _Q4_REDUCE]
-        red_g = max(b[2] for _, b in pairs)
-        sel = [(a, b) for a, b in pairs if b[2] == red_g]
+        """(mean value, dispatches, grid) of the finest-level shared-DoF
+        clearing and batch kernel and of the calibration copy (elementwise
+        kernel with the largest grid)."""
+        sel = _q4_pairs(rows)
         cp = [r for r in rows if "elementwise_kernel" in r[1]]
         cp_g = max(r[2] for r in cp)
         cp = [r for r in cp if r[2] == cp_g]
-        return {"vmult": (float(np.mean([a[3] for a, _ in sel])), len(sel), sel[0][0][2]),
-                "reduce": (float(np.mean([b[3] for _, b in sel])), len(sel), red_g),
+        return {"clear": (float(np.mean([a[3] for a, _ in sel])), len(sel), sel[0][0][2]),
+                "vmult": (float(np.mean([b[3] for _, b in sel])), len(sel), sel[0][1][2]),
                 "copy": (float(np.mean([r[3] for r in cp])), len(cp), cp_g)}
 
     res = {}
@@ -183,22 +186,22 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         res[label] = pick(_pmc_rows(folder, counter))
     f_fetch = 8.0 * n / (res["fetch"]["copy"][0] * 1024.0)
     f_write = 8.0 * n / (res["write"]["copy"][0] * 1024.0)
-    kib = {lab: res[lab]["vmult"][0] + res[lab]["reduce"][0] for lab in ("fetch", "write")}
+    kib = {lab: res[lab]["vmult"][0] + res[lab]["clear"][0] for lab in ("fetch", "write")}
     traffic = kib["fetch"] * 1024.0 * f_fetch + kib["write"] * 1024.0 * f_write
     alg = 16.0 * n
     lines = [
         "# HBM traffic of one operator application, 16^3 + 4 ball-step mesh, Q4, FP64",
         "",
         f"{n} free DoFs.  Two counter passes of the benchmark (the finest-level",
-        "applications are the (batch kernel, shared-DoF reduction) dispatch",
-        "pairs whose reduction has the largest grid), then this summary:",
+        "applications are the (shared-DoF clearing, batch kernel) dispatch",
+        "pairs whose clearing has the largest grid), then this summary:",
         "",
     ] + [f"    {c}" for c in commands] + [
         "",
         "| kernel | grid | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |",
         "|---|---:|---:|---:|---:|",
     ]
-    for key, name in (("vmult", "vmult_batch_kernel<4, double, double, 0, ...> (plain FP64 operator)"), ("reduce", _Q4_REDUCE),
+    for key, name in (("clear", _Q4_CLEAR), ("vmult", "vmult_batch_kernel<4, double, double, 3, ...> (plain FP64 operator)"),
                       ("copy", "elementwise kernel y = 1.0 * x (calibration, n doubles)")):
         fv, fd, fg = res["fetch"][key]
         wv, _, _ = res["write"][key]
@@ -644,7 +647,7 @@ def main():
                    "setup_s": round(setup_s, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
-                     "kernel": "vmult_batch_kernel + reduce_shared_kernel (one operator application)",
+                     "kernel": "clear_shared_kernel + vmult_batch_kernel (one operator application)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
     }
 

@@ -852,11 +852,15 @@ __device__ __forceinline__ CellGeo<T> cell_geo(const T* __restrict__ table, cons
   return g;
 }
 
+// the plain operator with the shared DoFs added to its output by global
+// atomics (chosen by the launcher; FUSE_NONE then means partial sums)
+constexpr int FUSE_NONE_ATOMIC = 3;
+
 // Final value t = (A x) of DoF g, vector v, and the fused step applied to it
 template <typename S, typename T, int FK>
 __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv, int v, T t, T* __restrict__ dst) {
   const int64_t e = g * nv + v;
-  if constexpr (FK == FUSE_NONE) {
+  if constexpr (FK == FUSE_NONE || FK == FUSE_NONE_ATOMIC) {
     dst[e] = t;
   } else if constexpr (FK == FUSE_RESIDUAL) {
     static_cast<S*>(f.r)[e] = store_as<S>(load_as<T>(static_cast<const S*>(f.b)[e]) - t);
@@ -878,8 +882,10 @@ __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv
 // are loaded into LDS (shared DoFs through their index list, exclusive DoFs as
 // one contiguous range), the cells are evaluated group by group from LDS and
 // their contributions accumulated in LDS, then the exclusive DoFs are stored
-// contiguously and the shared DoFs written as this batch's partial sums
-// (reduced afterwards).  gridDim.x is a multiple of 8.
+// contiguously and the shared DoFs either added to dst with global atomics
+// (FUSE_NONE_ATOMIC: the plain operator on one vector, dst's shared range
+// cleared before) or written as this batch's partial sums (reduced
+// afterwards).  gridDim.x is a multiple of 8.
 // register budget: 4 wavefronts per SIMD (two blocks per CU, as the LDS
 // allows); the operator of mapped cells, which holds three gradient
 // components and the metric terms of a line of points, gets the registers of
@@ -917,13 +923,19 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
   // lanes without a cell work on the block's spare buffers (results unused)
   T* B0 = buf0 + (lane_used ? wave * CPW + lc : BATCH_WAVES * CPW) * N3;
   const LaneLines ll = kLaneLines<K>.t[t];
-  const int gs0 = ll.zs0, gs1 = ll.zs1, gsm = ll.zsm, go0 = ll.zo0, gom = ll.zom, gst = ll.zst;
-  const int ss0 = ll.xs0, ss1 = ll.xs1, ssm = ll.xsm, so0 = ll.xo0, som = ll.xom, sst = ll.xst;
+  const int gsm = ll.zsm, go0 = ll.zo0, gom = ll.zom, gst = ll.zst;
+  const int ssm = ll.xsm, so0 = ll.xo0, som = ll.xom, sst = ll.xst;
+  // the six slots of the lane's z-line and x-line (each < 27), five bits
+  // apiece: the metadata fetch unpacks them each time instead of holding six
+  // 64-bit offsets through the batch loop
+  const uint32_t slots = ll.zs0 | (ll.zs1 << 5) | (ll.zsm << 10) | (ll.xs0 << 15) | (ll.xs1 << 20) |
+                         (static_cast<uint32_t>(ll.xsm) << 25);
   struct Pre {
     int g0, g1, gm, s0, s1, sm;
     uint32_t mask;
   };
 
+  if constexpr (FK == FUSE_NONE_ATOMIC) nv = 1;  // (one vector: the index arithmetic folds)
   const int64_t per = (nb + 7) / 8;
   const int64_t lo = (blockIdx.x % 8) * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
@@ -985,7 +997,10 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       const bool ok = lane_used && cell < c1;
       const CellMeta* M = META_LDS ? metaL + (ok ? cell - c0 : 0) : meta + (ok ? cell : c0);
       const uint16_t* L = M->loc;
-      Pre p{L[gs0], L[gs1], L[gsm], L[ss0], L[ss1], L[ssm], M->mask};
+      uint32_t sl = slots;
+      asm volatile("" : "+v"(sl));  // (keeps the unpacking here, not hoisted out of the loops)
+      Pre p{L[sl & 31u],         L[(sl >> 5) & 31u],  L[(sl >> 10) & 31u],
+            L[(sl >> 15) & 31u], L[(sl >> 20) & 31u], L[sl >> 25],         M->mask};
       p.g0 = ok ? p.g0 : ZB;
       p.g1 = ok ? p.g1 : ZB;
       p.gm = ok ? p.gm : ZB;
@@ -1066,17 +1081,28 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       }
       WaveSync{}();  // the next cell group reuses this wavefront's buffers
     }
-    // write back: the partial sums of the shared DoFs as one contiguous range
-    // (the batch's part of the partial buffer), exclusive DoFs in place
+    // write back: the shared DoFs' sums atomically into dst (their indices
+    // read again: keeping them in registers through the evaluation would
+    // spill) or as one contiguous range of partial sums (the batch's part of
+    // the partial buffer); exclusive DoFs in place
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = threadIdx.x + q * BT;
-      if (i < nsh) partial[static_cast<int64_t>(sh0 + i) * nv + v] = static_cast<T>(out_[i]);
-      else if (i < m) finish_dof<S, T, FK>(fs, ex0 + (i - nsh), nv, v, static_cast<T>(out_[i]), dst);
+      if (i < nsh) {
+        if constexpr (FK == FUSE_NONE_ATOMIC) unsafeAtomicAdd(&dst[sh_idx[sh0 + i]], static_cast<T>(out_[i]));
+        else partial[static_cast<int64_t>(sh0 + i) * nv + v] = static_cast<T>(out_[i]);
+      } else if (i < m) finish_dof<S, T, FK>(fs, ex0 + (i - nsh), nv, v, static_cast<T>(out_[i]), dst);
     }
     __syncthreads();  // the next batch or vector overwrites in_ and out_
   }
+}
+
+template <typename T>
+__global__ void clear_shared_kernel(int64_t n, T* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = T(0);
 }
 
 // (A x)_s = sum of the partial sums of shared DoF s, in the fixed order of its
@@ -1884,7 +1910,7 @@ void zero_bytes(void* p, int64_t bytes, hipStream_t s) {
 }
 
 template <int K, typename S, int FK, int GEO, bool DET>
-void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+void vmult_run(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
   using T = typename Acc<S>::type;
   constexpr int N = K + 1;
   if (c.n_cells == 0) return;
@@ -1911,15 +1937,39 @@ void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const Fuse
   int64_t blocks = 8 * ((nb * nv + 7) / 8);  // (several vectors: one block per (batch, vector) at most)
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
   if (blocks < 8 * nv) blocks = 8 * nv;  // every XCD runs all vectors of a batch together
-  vmult_batch_kernel<K, S, T, FK, GEO, DET><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
-      c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
-      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0, mt);
-  check_launch();
-  if (c.n_shared > 0) {
-    reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
-        c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
+  constexpr bool atom = FK == FUSE_NONE_ATOMIC;
+  if (atom && c.n_shared > 0) {  // (the shared DoFs are dst's first n_shared entries)
+    clear_shared_kernel<T><<<grid_for(c.n_shared), VEC_THREADS, 0, s>>>(c.n_shared, static_cast<T*>(dst));
     check_launch();
   }
+  vmult_batch_kernel<K, S, T, FK, GEO, DET><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
+      c.meta, c.batch_cell, c.batch_sh, c.batch_ex, c.sh_idx, nb, c.n_shared, c.h0, tab,
+      static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0,
+      mt);
+  check_launch();
+  if constexpr (!atom) {
+    if (c.n_shared > 0) {
+      reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
+          c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
+      check_launch();
+    }
+  }
+}
+
+// Shared DoFs of the plain operator on one vector go into dst with global
+// atomics, which run alongside the evaluation and replace the partial sums'
+// write and the reduction.  With a fused step, or with interleaved vectors
+// (whose atomics meet in one line), the partial sums measured faster; the
+// deterministic mode keeps their fixed order.
+template <int K, typename S, int FK, int GEO, bool DET>
+void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
+  if constexpr (FK == FUSE_NONE && !DET) {
+    if (nv == 1) {
+      vmult_run<K, S, FUSE_NONE_ATOMIC, GEO, false>(c, nv, dst, src, f, s);
+      return;
+    }
+  }
+  vmult_run<K, S, FK, GEO, DET>(c, nv, dst, src, f, s);
 }
 
 template <int K, typename S, int FK, int GEO>
