@@ -86,9 +86,9 @@ def _kname(name):
 
 
 # the plain FP64 Q4 operator on one vector, axis-aligned cells, default mode
-# (fused kind 3: no fused step, the shared DoFs' contributions added to the
+# (fused kind 4: no fused step, the shared DoFs' contributions added to the
 # output atomically) and the clearing of the output's shared DoFs before it
-_Q4_VMULT = re.compile(r"vmult_batch_kernel<4, double, double, 3(, 0)?(, false)?>$")
+_Q4_VMULT = re.compile(r"vmult_batch_kernel<4, double, double, 4(, 0)?(, false)?>$")
 _Q4_CLEAR = "clear_shared_kernel<double>"
 
 
@@ -201,7 +201,7 @@ def pmc_summary(fetch_dir, write_dir, n, commands):
         "| kernel | grid | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |",
         "|---|---:|---:|---:|---:|",
     ]
-    for key, name in (("clear", _Q4_CLEAR), ("vmult", "vmult_batch_kernel<4, double, double, 3, ...> (plain FP64 operator)"),
+    for key, name in (("clear", _Q4_CLEAR), ("vmult", "vmult_batch_kernel<4, double, double, 4, ...> (plain FP64 operator)"),
                       ("copy", "elementwise kernel y = 1.0 * x (calibration, n doubles)")):
         fv, fd, fg = res["fetch"][key]
         wv, _, _ = res["write"][key]

@@ -852,17 +852,20 @@ __device__ __forceinline__ CellGeo<T> cell_geo(const T* __restrict__ table, cons
   return g;
 }
 
-// the plain operator with the shared DoFs added to its output by global
-// atomics (chosen by the launcher; FUSE_NONE then means partial sums)
-constexpr int FUSE_NONE_ATOMIC = 3;
+// Shared-DoF route of the batch kernel, or-ed into the fused kind by the
+// launcher: the shared DoFs' sums are added with global atomics (into dst for
+// the plain operator, else into an accumulator that finish_shared_kernel
+// completes) instead of being written as partial sums
+constexpr int FUSE_ATOMIC = 4;
+constexpr int base_kind(int fk) { return fk & 3; }
 
 // Final value t = (A x) of DoF g, vector v, and the fused step applied to it
 template <typename S, typename T, int FK>
 __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv, int v, T t, T* __restrict__ dst) {
   const int64_t e = g * nv + v;
-  if constexpr (FK == FUSE_NONE || FK == FUSE_NONE_ATOMIC) {
+  if constexpr (base_kind(FK) == FUSE_NONE) {
     dst[e] = t;
-  } else if constexpr (FK == FUSE_RESIDUAL) {
+  } else if constexpr (base_kind(FK) == FUSE_RESIDUAL) {
     static_cast<S*>(f.r)[e] = store_as<S>(load_as<T>(static_cast<const S*>(f.b)[e]) - t);
   } else {
     S* d = static_cast<S*>(f.d);
@@ -882,10 +885,11 @@ __device__ __forceinline__ void finish_dof(const FusedStep& f, int64_t g, int nv
 // are loaded into LDS (shared DoFs through their index list, exclusive DoFs as
 // one contiguous range), the cells are evaluated group by group from LDS and
 // their contributions accumulated in LDS, then the exclusive DoFs are stored
-// contiguously and the shared DoFs either added to dst with global atomics
-// (FUSE_NONE_ATOMIC: the plain operator on one vector, dst's shared range
-// cleared before) or written as this batch's partial sums (reduced
-// afterwards).  gridDim.x is a multiple of 8.
+// contiguously and the shared DoFs either added with global atomics
+// (FUSE_ATOMIC route, one vector: into dst, or into the accumulator in the
+// partial buffer when a step is fused; either cleared before) or written as
+// this batch's partial sums (reduced afterwards).  gridDim.x is a multiple
+// of 8.
 // register budget: 4 wavefronts per SIMD (two blocks per CU, as the LDS
 // allows); the operator of mapped cells, which holds three gradient
 // components and the metric terms of a line of points, gets the registers of
@@ -935,7 +939,7 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
     uint32_t mask;
   };
 
-  if constexpr (FK == FUSE_NONE_ATOMIC) nv = 1;  // (one vector: the index arithmetic folds)
+  if constexpr ((FK & FUSE_ATOMIC) != 0) nv = 1;  // (one vector: the index arithmetic folds)
   const int64_t per = (nb + 7) / 8;
   const int64_t lo = (blockIdx.x % 8) * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
@@ -1081,16 +1085,18 @@ __global__ void __launch_bounds__(BATCH_WAVES * 64)
       }
       WaveSync{}();  // the next cell group reuses this wavefront's buffers
     }
-    // write back: the shared DoFs' sums atomically into dst (their indices
-    // read again: keeping them in registers through the evaluation would
-    // spill) or as one contiguous range of partial sums (the batch's part of
-    // the partial buffer); exclusive DoFs in place
+    // write back: the shared DoFs' sums atomically into dst or the
+    // accumulator (their indices read again: keeping them in registers
+    // through the evaluation would spill) or as one contiguous range of
+    // partial sums (the batch's part of the partial buffer); exclusive DoFs
+    // in place, with the fused step
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = threadIdx.x + q * BT;
       if (i < nsh) {
-        if constexpr (FK == FUSE_NONE_ATOMIC) unsafeAtomicAdd(&dst[sh_idx[sh0 + i]], static_cast<T>(out_[i]));
+        if constexpr ((FK & FUSE_ATOMIC) != 0)
+          unsafeAtomicAdd(&(base_kind(FK) == FUSE_NONE ? dst : partial)[sh_idx[sh0 + i]], static_cast<T>(out_[i]));
         else partial[static_cast<int64_t>(sh0 + i) * nv + v] = static_cast<T>(out_[i]);
       } else if (i < m) finish_dof<S, T, FK>(fs, ex0 + (i - nsh), nv, v, static_cast<T>(out_[i]), dst);
     }
@@ -1103,6 +1109,15 @@ __global__ void clear_shared_kernel(int64_t n, T* __restrict__ dst) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     dst[i] = T(0);
+}
+
+// the fused step on the shared DoFs of one vector, from their sums (A x)_s
+// accumulated atomically in acc
+template <typename S, typename T, int FK>
+__global__ void finish_shared_kernel(int64_t n_shared, const T* __restrict__ acc, T* __restrict__ dst, FusedStep fs) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_shared;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    finish_dof<S, T, FK>(fs, i, 1, 0, acc[i], dst);
 }
 
 // (A x)_s = sum of the partial sums of shared DoF s, in the fixed order of its
@@ -1937,9 +1952,11 @@ void vmult_run(const CellView& c, int nv, void* dst, const void* src, const Fuse
   int64_t blocks = 8 * ((nb * nv + 7) / 8);  // (several vectors: one block per (batch, vector) at most)
   if (resident >= 8 && blocks > resident / 8 * 8) blocks = resident / 8 * 8;
   if (blocks < 8 * nv) blocks = 8 * nv;  // every XCD runs all vectors of a batch together
-  constexpr bool atom = FK == FUSE_NONE_ATOMIC;
-  if (atom && c.n_shared > 0) {  // (the shared DoFs are dst's first n_shared entries)
-    clear_shared_kernel<T><<<grid_for(c.n_shared), VEC_THREADS, 0, s>>>(c.n_shared, static_cast<T*>(dst));
+  constexpr bool atom = (FK & FUSE_ATOMIC) != 0;
+  constexpr bool into_dst = base_kind(FK) == FUSE_NONE;
+  if (atom && c.n_shared > 0) {  // (the shared DoFs are the first n_shared)
+    clear_shared_kernel<T><<<grid_for(c.n_shared), VEC_THREADS, 0, s>>>(
+        c.n_shared, static_cast<T*>(into_dst ? dst : c.partial));
     check_launch();
   }
   vmult_batch_kernel<K, S, T, FK, GEO, DET><<<static_cast<unsigned>(blocks), BATCH_WAVES * 64, 0, s>>>(
@@ -1947,6 +1964,13 @@ void vmult_run(const CellView& c, int nv, void* dst, const void* src, const Fuse
       static_cast<const S*>(src), static_cast<T*>(c.partial), static_cast<T*>(dst), nv, f, geo, c.ijk, c.geo_n0,
       mt);
   check_launch();
+  if constexpr (atom && !into_dst) {
+    if (c.n_shared > 0) {
+      finish_shared_kernel<S, T, base_kind(FK)><<<grid_for(c.n_shared), VEC_THREADS, 0, s>>>(
+          c.n_shared, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
+      check_launch();
+    }
+  }
   if constexpr (!atom) {
     if (c.n_shared > 0) {
       reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
@@ -1956,16 +1980,16 @@ void vmult_run(const CellView& c, int nv, void* dst, const void* src, const Fuse
   }
 }
 
-// Shared DoFs of the plain operator on one vector go into dst with global
-// atomics, which run alongside the evaluation and replace the partial sums'
-// write and the reduction.  With a fused step, or with interleaved vectors
-// (whose atomics meet in one line), the partial sums measured faster; the
-// deterministic mode keeps their fixed order.
+// One vector: the shared DoFs' sums go out with global atomics, which run
+// alongside the evaluation and replace the partial sums' write and the
+// reduction's gathers.  Interleaved vectors keep the partial sums (their
+// atomics would meet in one line, which measured slower), and so does the
+// deterministic mode (their fixed order).
 template <int K, typename S, int FK, int GEO, bool DET>
 void vmult_kgd(const CellView& c, int nv, void* dst, const void* src, const FusedStep& f, hipStream_t s) {
-  if constexpr (FK == FUSE_NONE && !DET) {
+  if constexpr (!DET) {
     if (nv == 1) {
-      vmult_run<K, S, FUSE_NONE_ATOMIC, GEO, false>(c, nv, dst, src, f, s);
+      vmult_run<K, S, FK | FUSE_ATOMIC, GEO, false>(c, nv, dst, src, f, s);
       return;
     }
   }

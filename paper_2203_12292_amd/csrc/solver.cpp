@@ -519,9 +519,9 @@ void level_smooth(Context& ctx, int l, int nv, void* x, const void* b, bool x_is
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   // each operator application on one vector carries the Chebyshev update of
-  // its output (exclusive DoFs in the batch kernel, shared DoFs in the
-  // reduction); several interleaved vectors, which the operator handles one
-  // after the other, are updated by the contiguous vector kernel instead
+  // its output (exclusive DoFs in the batch kernel, shared DoFs in the pass
+  // after it); several interleaved vectors are updated by the contiguous
+  // vector kernel instead
   if (nv > 1) {
     if (x_is_zero) {
       launch_cheb_step(dt, L.n_dofs, nv, true, 0.0, 1.0 / theta, nullptr, b, dinv, L.d.ptr, x, s);
