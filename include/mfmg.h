@@ -183,15 +183,17 @@ typedef struct {
   int deterministic;     /* 1: repeated calls give bitwise identical results
                             (for debugging; slower).  The operator adds its
                             cells' contributions to a batch in cell order,
-                            one cell at a time; the restriction, the
-                            diagonal and the load vector run colour by
-                            colour (no two cells or transfer groups of a
-                            colour share an entity) with plain adds instead
-                            of atomics.  Everything else on the solve path
-                            (shared-DoF reduction, prolongation, dot
-                            products, coarse solve) has a fixed order
-                            anyway.  Not covered: the learned correction's
-                            inference and training.  0: atomics (default). */
+                            one cell at a time, and sums the DoFs shared
+                            between batches from per-batch partial sums in
+                            a fixed order; the restriction, the diagonal
+                            and the load vector run colour by colour (no
+                            two cells or transfer groups of a colour share
+                            an entity) with plain adds instead of atomics.
+                            Everything else on the solve path
+                            (prolongation, dot products, coarse solve) has
+                            a fixed order anyway.  Not covered: the learned
+                            correction's inference and training.  0:
+                            atomics (default). */
 } mfmg_level_desc;
 
 typedef struct {
