@@ -842,7 +842,7 @@ def main():
         out["roofline_q6_fp32_8vec"] = {
             "bound": "hbm", "achieved": alg4 / (ms4 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "vmult_batch_kernel<6, float> + reduce_shared_kernel, 8 interleaved vectors",
+            "kernel": "vmult_batch_kernel<6, float> + reduce_shared_vec_kernel, 8 interleaved vectors",
             "alg_bytes_per_launch": alg4, "avg_launch_ms": ms4, "dofs_per_s": 8 * n4 / (ms4 * 1e-3)}
         del x32, y32
         solves["cube12_spheres_q6_pmg_8rhs_fp32_vcycle"] = {

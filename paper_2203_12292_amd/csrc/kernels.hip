@@ -1139,6 +1139,24 @@ __global__ void reduce_shared_kernel(int64_t n_shared, int nv, const int32_t* __
   }
 }
 
+// The same for NV interleaved vectors, one thread per shared DoF: the NV
+// values of a partial sum are one aligned vector load, its index is read once
+// for all of them, and every value is summed in the same order as above
+template <typename S, typename T, int FK, int NV>
+__global__ void reduce_shared_vec_kernel(int64_t n_shared, const int32_t* __restrict__ red_off,
+                                         const int32_t* __restrict__ red_idx, const T* __restrict__ partial,
+                                         T* __restrict__ dst, FusedStep fs) {
+  typedef T VecT __attribute__((ext_vector_type(NV)));
+  for (int64_t sd = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; sd < n_shared;
+       sd += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    VecT acc = T(0);
+    for (int j = red_off[sd]; j < red_off[sd + 1]; ++j)
+      acc += *reinterpret_cast<const VecT*>(partial + static_cast<int64_t>(red_idx[j]) * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) finish_dof<S, T, FK>(fs, sd, NV, v, acc[v], dst);
+  }
+}
+
 // Does the hanging-node interpolation C_e touch node (a, b, c)?  Only if one
 // of the three lines through the node is interpolated: otherwise C_e e_s =
 // e_s for its slot s (the in-place line interpolations mix values along
@@ -1973,8 +1991,19 @@ void vmult_run(const CellView& c, int nv, void* dst, const void* src, const Fuse
   }
   if constexpr (!atom) {
     if (c.n_shared > 0) {
-      reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
-          c.n_shared, nv, c.red_off, c.red_idx, static_cast<const T*>(c.partial), static_cast<T*>(dst), f);
+      const T* part = static_cast<const T*>(c.partial);  // (256-byte aligned: vector loads of NV values)
+      T* out = static_cast<T*>(dst);
+      const unsigned g = grid_for(c.n_shared);
+      if (nv == 8) {
+        reduce_shared_vec_kernel<S, T, FK, 8><<<g, VEC_THREADS, 0, s>>>(c.n_shared, c.red_off, c.red_idx, part, out, f);
+      } else if (nv == 4) {
+        reduce_shared_vec_kernel<S, T, FK, 4><<<g, VEC_THREADS, 0, s>>>(c.n_shared, c.red_off, c.red_idx, part, out, f);
+      } else if (nv == 2) {
+        reduce_shared_vec_kernel<S, T, FK, 2><<<g, VEC_THREADS, 0, s>>>(c.n_shared, c.red_off, c.red_idx, part, out, f);
+      } else {
+        reduce_shared_kernel<S, T, FK><<<grid_for(c.n_shared * nv), VEC_THREADS, 0, s>>>(
+            c.n_shared, nv, c.red_off, c.red_idx, part, out, f);
+      }
       check_launch();
     }
   }
