@@ -76,3 +76,15 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     traffic = float(text.split("traffic_bytes_per_launch:")[1].split()[0])
     assert traffic == pytest.approx((100.0 * 2.0 + 50.0 + 300.0) * 1024.0)
     assert "source_sha256: " + bench.operator_source_digest() in text
+
+
+def test_recorded_traffic_follows_the_source_digest(tmp_path, monkeypatch):
+    """The bench line reports the committed traffic only while the operator
+    sources hash to the digest the summary was taken with."""
+    f = tmp_path / "traffic.md"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.recorded_traffic() is None  # no summary
+    f.write_text(f"traffic_bytes_per_launch: 1234\nsource_sha256: {bench.operator_source_digest()}\n")
+    assert bench.recorded_traffic() == 1234.0
+    f.write_text("traffic_bytes_per_launch: 1234\nsource_sha256: " + "0" * 64 + "\n")
+    assert bench.recorded_traffic() is None  # sources changed since
